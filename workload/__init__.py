@@ -1,0 +1,154 @@
+"""Seeded synthetic inputs shared by the FP64 oracle and the GPU path.
+
+This module holds problem descriptions and input data only: the subdomain
+partition and point counts, the random hidden-layer parameters (which the
+method draws once, before anything else), and closed-form manufactured
+solutions with their sources.  It contains none of the method's arithmetic
+(no features, no least squares, no interface system), so the oracle and the
+GPU library can both take their inputs from here without sharing any solver
+code.
+
+Problem setting: the elliptic problem L u = f in a rectangle with Dirichlet
+data u = g on the boundary (paper, Section 2, eq. pde), with L = -Laplace
+(Section 4.2, eq. poisson) or L u = -div(a grad u) (Section 4.2, variable
+coefficient problem).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+OP_POISSON = 0
+OP_VARCOEF = 1
+
+
+@dataclasses.dataclass(frozen=True)
+class Problem:
+    """One elliptic problem on a rectangle split into nsub_x x nsub_y subdomains.
+
+    neurons      -- hidden neurons of every local network (n_N in Section 3)
+    q_x, q_y     -- interior collocation grid per subdomain (cell-centred)
+    m_bdry_edge  -- collocation points per exterior (Dirichlet) edge
+    m_ifc_edge   -- interface points per interface edge
+    op           -- OP_POISSON or OP_VARCOEF
+    R            -- hidden weights and biases are i.i.d. U[-R, R]
+    k1, k2       -- wave numbers of the variable coefficient a(x, y)
+    """
+
+    nsub_x: int
+    nsub_y: int
+    neurons: int
+    q_x: int
+    q_y: int
+    m_bdry_edge: int
+    m_ifc_edge: int
+    op: int = OP_POISSON
+    R: float = 1.0
+    k1: int = 1
+    k2: int = 1
+    x0: float = 0.0
+    x1: float = 1.0
+    y0: float = 0.0
+    y1: float = 1.0
+
+    @property
+    def nsub(self) -> int:
+        return self.nsub_x * self.nsub_y
+
+    @property
+    def n_interface(self) -> int:
+        """Number of interface unknowns (one per interface point)."""
+        nv = (self.nsub_x - 1) * self.nsub_y
+        nh = self.nsub_x * (self.nsub_y - 1)
+        return (nv + nh) * self.m_ifc_edge
+
+
+# The small 2x2 case: 100 tanh neurons per subdomain, U[-2,2], 20x20 interior
+# points, 40 points per exterior edge, 20 per interface edge.
+CONFIG_SMALL = Problem(nsub_x=2, nsub_y=2, neurons=100, q_x=20, q_y=20,
+                       m_bdry_edge=40, m_ifc_edge=20, R=2.0)
+# The 8x8 case: 400 neurons per subdomain, U[-4,4], 40x40 interior points,
+# 40 points per edge (exterior and interface).
+CONFIG_8x8 = Problem(nsub_x=8, nsub_y=8, neurons=400, q_x=40, q_y=40,
+                     m_bdry_edge=40, m_ifc_edge=40, R=4.0)
+
+
+def hidden_params(problem: Problem, seed: int):
+    """Random hidden layer of every local network.
+
+    Returns W of shape (nsub, n, 2) and b of shape (nsub, n), all i.i.d.
+    U[-R, R] (weights act on subdomain-local coordinates in [-1, 1]^2).
+    The method fixes these once and never trains them (Section 2.2, ELM).
+    """
+    rng = np.random.default_rng(seed)
+    R = problem.R
+    N, n = problem.nsub, problem.neurons
+    W = rng.uniform(-R, R, size=(N, n, 2))
+    b = rng.uniform(-R, R, size=(N, n))
+    return np.ascontiguousarray(W), np.ascontiguousarray(b)
+
+
+# ---------------------------------------------------------------------------
+# Manufactured solution u* = sin(pi x) sin(pi y) and its data.
+# ---------------------------------------------------------------------------
+
+def exact_u(problem: Problem, x, y):
+    return np.sin(math.pi * x) * np.sin(math.pi * y)
+
+
+def coefficient(problem: Problem, x, y):
+    """a, da/dx, da/dy of a = 1 + 0.5 sin(2 pi k1 x) cos(2 pi k2 y); a = 1 for Poisson."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    if problem.op == OP_POISSON:
+        one = np.ones_like(x)
+        return one, np.zeros_like(x), np.zeros_like(x)
+    w1 = 2.0 * math.pi * problem.k1
+    w2 = 2.0 * math.pi * problem.k2
+    a = 1.0 + 0.5 * np.sin(w1 * x) * np.cos(w2 * y)
+    ax = 0.5 * w1 * np.cos(w1 * x) * np.cos(w2 * y)
+    ay = -0.5 * w2 * np.sin(w1 * x) * np.sin(w2 * y)
+    return a, ax, ay
+
+
+def source_f(problem: Problem, x, y):
+    """f = L u* for u* = sin(pi x) sin(pi y).
+
+    Poisson: f = 2 pi^2 u*.  Variable coefficient:
+    f = -a Lap u* - grad a . grad u* (product rule).
+    """
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    p = math.pi
+    u = np.sin(p * x) * np.sin(p * y)
+    if problem.op == OP_POISSON:
+        return 2.0 * p * p * u
+    a, ax, ay = coefficient(problem, x, y)
+    ux = p * np.cos(p * x) * np.sin(p * y)
+    uy = p * np.sin(p * x) * np.cos(p * y)
+    return a * (2.0 * p * p * u) - (ax * ux + ay * uy)
+
+
+def boundary_g(problem: Problem, x, y):
+    """Dirichlet data g = u* on the boundary."""
+    return exact_u(problem, x, y)
+
+
+def eval_grid(problem: Problem, per_sub: int = 16):
+    """Cell-centred per_sub x per_sub evaluation points in every subdomain.
+
+    Returns (x, y) flattened subdomain-major (subdomain s = sy * nsub_x + sx,
+    then row-major in y, then x).
+    """
+    hx = (problem.x1 - problem.x0) / problem.nsub_x
+    hy = (problem.y1 - problem.y0) / problem.nsub_y
+    t = (np.arange(per_sub) + 0.5) / per_sub
+    xs, ys = [], []
+    for sy in range(problem.nsub_y):
+        for sx in range(problem.nsub_x):
+            X, Y = np.meshgrid(problem.x0 + (sx + t) * hx, problem.y0 + (sy + t) * hy)
+            xs.append(X.ravel())
+            ys.append(Y.ravel())
+    return np.concatenate(xs), np.concatenate(ys)
