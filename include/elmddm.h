@@ -1,0 +1,190 @@
+/*
+ * elmddm -- nonoverlapping domain decomposition for extreme learning machines
+ * (one-hidden-layer tanh networks, one per subdomain) on a single AMD MI355X
+ * (gfx950).  C ABI: plain pointers and sizes, no C++ or framework types.
+ *
+ * The method (paper, Section 3 and Algorithm 1): for
+ *     L u = f in the rectangle [x0,x1] x [y0,y1],   u = g on its boundary
+ * (Section 2, eq. pde; L = -Laplace or L u = -div(a grad u), Section 4.2), the
+ * rectangle is split into nsub_x x nsub_y equal boxes.  Each box s carries a
+ * network u_s(x) = sum_j c_j tanh(w_j . xhat + b_j) with fixed random hidden
+ * parameters (w_j, b_j) acting on box-local coordinates
+ * xhat = 2 (x - x_center)/h_x, yhat = 2 (y - y_center)/h_y  in [-1, 1]^2.
+ * The local least-squares blocks K^s, A^s, B^s, F^s (eq. nonoverlap_discrete)
+ * are coupled through one auxiliary unknown u_Gamma per interface point; the
+ * library eliminates the output-layer coefficients c, solves the interface
+ * Schur complement system (eq. schur) for u_Gamma, and back-solves every
+ * K^{sT} K^s c^s = K^{sT} (F^s - B^s u_Gamma).
+ *
+ * Point layout (the paper leaves it open; this is the library's reading):
+ *  - interior points: cell-centred q_x x q_y grid per box, row-major (y outer);
+ *  - every box edge carries points at the midpoints (k + 1/2)/m of m equal
+ *    pieces: m_bdry_edge Dirichlet points on an outer edge, m_ifc_edge
+ *    interface points on an edge shared by two boxes; box corners carry none,
+ *    so every interface point has exactly two owners and one flux row;
+ *  - boxes are numbered s = sy * nsub_x + sx; per box the edges are visited
+ *    bottom, right, top, left;
+ *  - interface numbering: all vertical interface edges (edge row outer,
+ *    x inner), then all horizontal ones; points along an edge by increasing
+ *    coordinate.
+ *
+ * Memory: every device pointer is caller-owned device memory on the current
+ * HIP device, float64 unless stated.  A plan owns its own device workspace,
+ * allocated by elmddm_plan_create and released by elmddm_plan_destroy; no
+ * solve call allocates.  Every device call is enqueued on the caller's HIP
+ * stream (hipStream_t passed as void*, NULL = default stream) and returns
+ * after enqueueing; results are valid after the stream is synchronised.  A
+ * plan may be used by one stream at a time.
+ *
+ * Errors: functions return an elmddm_status.  Argument errors are detected
+ * on the host before anything is enqueued.  Numerical failures found on the
+ * device (a local Gram block or the Schur matrix not positive definite,
+ * non-finite values) are recorded in the plan and returned by
+ * elmddm_solve_info after synchronisation.  elmddm_last_error() gives a
+ * human-readable message for the last failing call on the calling thread.
+ */
+#ifndef ELMDDM_H
+#define ELMDDM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum elmddm_status {
+    ELMDDM_OK = 0,
+    ELMDDM_INVALID_ARG = 1,
+    ELMDDM_OOM = 2,
+    ELMDDM_NOT_SPD = 3,        /* a local Gram matrix lost positive definiteness */
+    ELMDDM_SCHUR_NOT_SPD = 4,  /* the interface Schur matrix lost positive definiteness */
+    ELMDDM_NOT_CONVERGED = 5,
+    ELMDDM_NONFINITE = 6,
+    ELMDDM_HIP_ERROR = 7,
+    ELMDDM_UNSUPPORTED = 8
+} elmddm_status;
+
+enum { ELMDDM_OP_POISSON = 0, ELMDDM_OP_VARCOEF = 1 };
+
+enum {
+    ELMDDM_POINTS_INTERIOR = 0,   /* nsub * q_x * q_y points, box-major          */
+    ELMDDM_POINTS_BOUNDARY = 1,   /* all Dirichlet points, box-major, local order */
+    ELMDDM_POINTS_INTERFACE = 2   /* n_interface points, global interface order   */
+};
+
+/* Problem statement (Section 2, eq. pde, and Section 3): domain, operator,
+ * partition, neurons and collocation points per subdomain. */
+typedef struct elmddm_problem {
+    double x0, x1, y0, y1;   /* the rectangle                                   */
+    int32_t nsub_x, nsub_y;  /* subdomain grid                                  */
+    int32_t neurons;         /* hidden neurons per local network (n_N), >= 1    */
+    int32_t q_x, q_y;        /* interior collocation grid per subdomain         */
+    int32_t m_bdry_edge;     /* Dirichlet points per outer edge, >= 1           */
+    int32_t m_ifc_edge;      /* interface points per interface edge, >= 1      */
+    int32_t op;              /* ELMDDM_OP_POISSON or ELMDDM_OP_VARCOEF          */
+} elmddm_problem;
+
+/* Sizes derived from a problem (filled by elmddm_plan_sizes). */
+typedef struct elmddm_sizes {
+    int32_t nsub;            /* number of subdomains N                          */
+    int32_t neurons;         /* n_N                                             */
+    int32_t n_interior;      /* interior points per subdomain (q_x * q_y)       */
+    int32_t n_interface;     /* interface unknowns nG                           */
+    int64_t n_boundary;      /* Dirichlet points over all subdomains            */
+    int32_t max_rows;        /* largest local row count m_s                     */
+    int32_t max_ifc;         /* largest local interface count k_s               */
+    uint64_t device_bytes;   /* device memory owned by the plan                 */
+} elmddm_sizes;
+
+/* Per-solve diagnostics (filled by elmddm_solve_info). */
+typedef struct elmddm_info {
+    int32_t status;          /* elmddm_status of the last solve                 */
+    int32_t bad_subdomain;   /* first subdomain whose local factorisation failed, else -1 */
+    int32_t bad_pass;        /* CholeskyQR pass (1..3) of that failure, else 0  */
+    int32_t reserved;
+} elmddm_info;
+
+typedef struct elmddm_plan elmddm_plan;
+
+/* Validate the problem, build the point layout and interface maps on the host
+ * and allocate the plan's device workspace on the current device.
+ * Requires q_x * q_y >= neurons (the Proposition of Section 3 needs at least
+ * as many interior points as neurons per subdomain); otherwise INVALID_ARG.
+ * On failure *plan is set to NULL. */
+elmddm_status elmddm_plan_create(const elmddm_problem* problem, elmddm_plan** plan);
+
+/* Release the plan and its device memory.  NULL is accepted. */
+elmddm_status elmddm_plan_destroy(elmddm_plan* plan);
+
+elmddm_status elmddm_plan_sizes(const elmddm_plan* plan, elmddm_sizes* sizes);
+
+/* Host copy of the plan's points of one kind (see ELMDDM_POINTS_*), as
+ * interleaved (x, y) pairs in the documented order.  capacity is the number
+ * of points xy can hold; fails with INVALID_ARG if too small.  Callers use
+ * these points to sample f, g and the coefficient a. */
+elmddm_status elmddm_points(const elmddm_plan* plan, int32_t kind, double* xy, int64_t capacity);
+
+/* Algorithm 1 (Section 3) end to end on the device:
+ *   W     [nsub][neurons][2]  hidden weights (w_x, w_y) on box-local coordinates
+ *   b     [nsub][neurons]     hidden biases
+ *   f     [nsub][q_x*q_y]     source at the interior points (ELMDDM_POINTS_INTERIOR order)
+ *   g     [n_boundary]        Dirichlet data at the boundary points (ELMDDM_POINTS_BOUNDARY order)
+ *   coef  [3][nsub][q_x*q_y]  a, da/dx, da/dy at the interior points (VARCOEF only; else NULL)
+ *   u_gamma [n_interface]     output: interface variable
+ *   c     [nsub][neurons]     output: output-layer coefficients of every local network
+ * Local least squares: three-pass shifted CholeskyQR in float64 (Gram by
+ * MFMA, Cholesky, triangular solves); interface system: dense float64
+ * Cholesky.  Enqueued on stream; check elmddm_solve_info afterwards. */
+elmddm_status elmddm_solve(elmddm_plan* plan, const double* W, const double* b, const double* f,
+                           const double* g, const double* coef, double* u_gamma, double* c,
+                           void* stream);
+
+/* Synchronise the stream of the last solve and report its device-side status. */
+elmddm_status elmddm_solve_info(elmddm_plan* plan, elmddm_info* info);
+
+/* Network solution u_h at npts arbitrary points xy [npts][2] (device): each
+ * point is evaluated by the local network of the box that holds it (boxes
+ * half-open, the last one closed).  Writes u [npts] (device). */
+elmddm_status elmddm_eval(elmddm_plan* plan, const double* W, const double* b, const double* c,
+                          const double* xy, int64_t npts, double* u, void* stream);
+
+/* The feature-assembly stage alone (the rows of eq. nonoverlap_discrete):
+ * writes, per subdomain s, K^s in column-major [nsub][neurons][max_rows]
+ * (rows: interior, boundary, interface; rows beyond m_s are zero), the flux
+ * rows A^s column-major [nsub][neurons][max_ifc] (outward normal
+ * derivatives at the interface points; rows beyond k_s zero) and
+ * F^s [nsub][max_rows].  For checking the assembly; not needed to solve. */
+elmddm_status elmddm_assemble(elmddm_plan* plan, const double* W, const double* b, const double* f,
+                              const double* g, const double* coef, double* K, double* A, double* F,
+                              void* stream);
+
+/* Copy the interface Schur matrix S [n_interface][n_interface] (column-major)
+ * and its right-hand side [n_interface] of eq. schur, as assembled by the
+ * last elmddm_solve, into caller device buffers.  Valid only if the plan was
+ * told to keep them with elmddm_plan_keep_schur(plan, 1) before that solve. */
+elmddm_status elmddm_plan_keep_schur(elmddm_plan* plan, int32_t keep);
+elmddm_status elmddm_get_schur(elmddm_plan* plan, double* S, double* rhs, void* stream);
+
+/* Per-stage device timing of solves (HIP events recorded on the solve's
+ * stream around each stage).  When enabled, every elmddm_solve adds the
+ * elapsed time of each stage to running totals; elmddm_stage_times
+ * synchronises the last solve's stream and reads the totals (milliseconds)
+ * and the number of solves they cover.  Stages:
+ *   0 feature assembly            1 Gram matrices (3 MFMA SYRK launches)
+ *   2 local Cholesky + inverses   3 triangular solves (3 MFMA GEMM launches)
+ *   4 Schur complement assembly   5 interface Cholesky
+ *   6 interface back-substitution 7 local back-solve
+ * Enabling resets the totals. */
+#define ELMDDM_NUM_STAGES 8
+elmddm_status elmddm_set_timing(elmddm_plan* plan, int32_t enable);
+elmddm_status elmddm_stage_times(elmddm_plan* plan, double* ms, int32_t* solves);
+
+const char* elmddm_status_string(elmddm_status status);
+const char* elmddm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ELMDDM_H */

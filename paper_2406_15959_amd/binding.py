@@ -1,0 +1,189 @@
+"""Thin ctypes binding of libelmddm (argument marshalling only).
+
+Every computation runs in the HIP library; this module only converts
+torch device tensors into pointers and the current torch stream into a
+hipStream_t.  It fails loudly if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libelmddm.so")
+
+OK = 0
+INVALID_ARG = 1
+OOM = 2
+NOT_SPD = 3
+SCHUR_NOT_SPD = 4
+NOT_CONVERGED = 5
+NONFINITE = 6
+HIP_ERROR = 7
+UNSUPPORTED = 8
+
+OP_POISSON = 0
+OP_VARCOEF = 1
+POINTS_INTERIOR = 0
+POINTS_BOUNDARY = 1
+POINTS_INTERFACE = 2
+
+EXPORTED = [
+    "elmddm_plan_create", "elmddm_plan_destroy", "elmddm_plan_sizes", "elmddm_points",
+    "elmddm_solve", "elmddm_solve_info", "elmddm_eval", "elmddm_assemble",
+    "elmddm_plan_keep_schur", "elmddm_get_schur", "elmddm_set_timing", "elmddm_stage_times",
+    "elmddm_status_string", "elmddm_last_error",
+]
+
+NUM_STAGES = 8
+STAGE_NAMES = ["assembly", "gram_syrk", "local_cholesky", "local_trsm", "schur_assembly",
+               "interface_cholesky", "interface_backsub", "local_backsolve"]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("x0", ctypes.c_double), ("x1", ctypes.c_double), ("y0", ctypes.c_double),
+                ("y1", ctypes.c_double), ("nsub_x", ctypes.c_int32), ("nsub_y", ctypes.c_int32),
+                ("neurons", ctypes.c_int32), ("q_x", ctypes.c_int32), ("q_y", ctypes.c_int32),
+                ("m_bdry_edge", ctypes.c_int32), ("m_ifc_edge", ctypes.c_int32), ("op", ctypes.c_int32)]
+
+
+class Sizes(ctypes.Structure):
+    _fields_ = [("nsub", ctypes.c_int32), ("neurons", ctypes.c_int32), ("n_interior", ctypes.c_int32),
+                ("n_interface", ctypes.c_int32), ("n_boundary", ctypes.c_int64),
+                ("max_rows", ctypes.c_int32), ("max_ifc", ctypes.c_int32),
+                ("device_bytes", ctypes.c_uint64)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("bad_subdomain", ctypes.c_int32),
+                ("bad_pass", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class ElmddmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"elmddm status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libelmddm.so (built in-tree); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise ImportError(f"{_LIB_PATH} is missing: build it with python -m paper_2406_15959_amd.build")
+        L = ctypes.CDLL(_LIB_PATH)
+        vp, dp, i32, i64 = ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.elmddm_plan_create.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(vp)]
+        L.elmddm_plan_destroy.argtypes = [vp]
+        L.elmddm_plan_sizes.argtypes = [vp, ctypes.POINTER(Sizes)]
+        L.elmddm_points.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), i64]
+        L.elmddm_solve.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp, vp]
+        L.elmddm_solve_info.argtypes = [vp, ctypes.POINTER(Info)]
+        L.elmddm_eval.argtypes = [vp, dp, dp, dp, dp, i64, dp, vp]
+        L.elmddm_assemble.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp, dp, vp]
+        L.elmddm_plan_keep_schur.argtypes = [vp, i32]
+        L.elmddm_get_schur.argtypes = [vp, dp, dp, vp]
+        L.elmddm_set_timing.argtypes = [vp, i32]
+        L.elmddm_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]
+        L.elmddm_status_string.argtypes = [i32]
+        L.elmddm_status_string.restype = ctypes.c_char_p
+        L.elmddm_last_error.restype = ctypes.c_char_p
+        for name in EXPORTED:
+            if name not in ("elmddm_status_string", "elmddm_last_error"):
+                getattr(L, name).restype = i32
+        _lib = L
+    return _lib
+
+
+def _check(st):
+    if st != OK:
+        L = lib()
+        raise ElmddmError(st, f"{L.elmddm_status_string(st).decode()}: {L.elmddm_last_error().decode()}")
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    import torch
+    assert isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous(), \
+        "expected a contiguous float64 CUDA tensor"
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def make_problem(x0=0.0, x1=1.0, y0=0.0, y1=1.0, nsub_x=1, nsub_y=1, neurons=1, q_x=1, q_y=1,
+                 m_bdry_edge=1, m_ifc_edge=1, op=OP_POISSON) -> Problem:
+    return Problem(x0, x1, y0, y1, nsub_x, nsub_y, neurons, q_x, q_y, m_bdry_edge, m_ifc_edge, op)
+
+
+class Plan:
+    """Owns an elmddm_plan (host layout + device workspace)."""
+
+    def __init__(self, problem: Problem):
+        self._h = ctypes.c_void_p()
+        _check(lib().elmddm_plan_create(ctypes.byref(problem), ctypes.byref(self._h)))
+        s = Sizes()
+        _check(lib().elmddm_plan_sizes(self._h, ctypes.byref(s)))
+        self.sizes = s
+        self.problem = problem
+
+    def close(self):
+        if self._h:
+            lib().elmddm_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def points(self, kind) -> np.ndarray:
+        s = self.sizes
+        count = {POINTS_INTERIOR: s.nsub * s.n_interior, POINTS_BOUNDARY: s.n_boundary,
+                 POINTS_INTERFACE: s.n_interface}[kind]
+        out = np.zeros((max(count, 1), 2), dtype=np.float64)
+        _check(lib().elmddm_points(self._h, kind, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   max(count, 1)))
+        return out[:count]
+
+    def solve(self, W, b, f, g, coef, u_gamma, c):
+        _check(lib().elmddm_solve(self._h, _ptr(W), _ptr(b), _ptr(f), _ptr(g), _ptr(coef),
+                                  _ptr(u_gamma), _ptr(c), _stream()))
+
+    def solve_info(self) -> Info:
+        info = Info()
+        _check(lib().elmddm_solve_info(self._h, ctypes.byref(info)))
+        return info
+
+    def eval(self, W, b, c, xy, u):
+        _check(lib().elmddm_eval(self._h, _ptr(W), _ptr(b), _ptr(c), _ptr(xy), xy.shape[0], _ptr(u),
+                                 _stream()))
+
+    def assemble(self, W, b, f, g, coef, K, A, F):
+        _check(lib().elmddm_assemble(self._h, _ptr(W), _ptr(b), _ptr(f), _ptr(g), _ptr(coef),
+                                     _ptr(K), _ptr(A), _ptr(F), _stream()))
+
+    def keep_schur(self, keep=True):
+        _check(lib().elmddm_plan_keep_schur(self._h, 1 if keep else 0))
+
+    def set_timing(self, enable=True):
+        _check(lib().elmddm_set_timing(self._h, 1 if enable else 0))
+
+    def stage_times(self):
+        """(milliseconds per stage summed over timed solves, number of timed solves)."""
+        ms = (ctypes.c_double * NUM_STAGES)()
+        n = ctypes.c_int32()
+        _check(lib().elmddm_stage_times(self._h, ms, ctypes.byref(n)))
+        return list(ms), n.value
+
+    def get_schur(self, S, rhs):
+        _check(lib().elmddm_get_schur(self._h, _ptr(S), _ptr(rhs), _stream()))

@@ -1,0 +1,107 @@
+// Internal interfaces between the host plan code and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace elmddm {
+
+// Row kinds of the per-subdomain row table (one entry per row of X).
+enum RowKind : int32_t {
+    ROW_ZERO = 0,       // padding row: all zero
+    ROW_INTERIOR = 1,   // operator row L phi at an interior point, rhs = f
+    ROW_BOUNDARY = 2,   // value row phi at a Dirichlet point, rhs = g
+    ROW_IFC_VALUE = 3,  // value row phi at an interface point, rhs = 0
+    ROW_FLUX = 4        // outward normal derivative at an interface point, rhs = 0
+};
+
+struct RowTable {
+    const double* x;      // [N][ldx] physical coordinates
+    const double* y;
+    const double* nx;     // outward normal (flux rows)
+    const double* ny;
+    const int32_t* kind;  // RowKind
+    const int32_t* src;   // index into f (interior: s*q2 + i) or g (boundary)
+    const int32_t* cmap;  // compact row: >= 0 row of K^s, <= -2 row (-2 - cmap) of A^s, -1 none
+};
+
+struct SubGeom {
+    const double* cx;     // [N] box centre
+    const double* cy;
+    double sx, sy;        // chain-rule factors 2/h_x, 2/h_y
+};
+
+// Device status record written by kernels.
+struct DevInfo {
+    int32_t status;
+    int32_t bad_subdomain;
+    int32_t bad_pass;
+    int32_t pad;
+};
+
+// ---- launchers (kernels.hip) ----
+
+// C = alpha * op(A) * op(B) + beta * C for a batch of column-major matrices.
+// op(A) is M x K (ta: A stored K x M), op(B) is K x N (tb: B stored N x K).
+// kmode 0: full K range; 1: op(B)(k, j) == 0 for k < j (skip k below the tile's first column);
+// 2: op(B)(k, j) == 0 for k > j (stop at the tile's last column).
+// lower: only output tiles on or below the diagonal (M, N share the tile grid).
+void gemm_f64(hipStream_t st, bool ta, bool tb, int kmode, bool lower, int M, int N, int K,
+              double alpha, const double* A, int lda, long long sA, const double* B, int ldb,
+              long long sB, double beta, double* C, int ldc, long long sC, int batch);
+
+// Writes X (plan layout, ldx rows x (n+1) columns per subdomain) or, if Kout != nullptr,
+// the compact K^s [n][ldK], A^s [n][ldD] and F^s [ldF] per subdomain.
+void assemble(hipStream_t st, int N, int ldx, int n, const RowTable& rows, const SubGeom& geom,
+              int op, const double* W, const double* b, const double* f, const double* g,
+              const double* coef, int q2, double* X, double* Fout, int ldF, double* Kout, int ldK,
+              double* Dout, int ldD);
+
+void scale_diag(hipStream_t st, double* A, int lda, long long sA, int n, double factor, int batch);
+
+// Factor the jb x jb diagonal block at (j, j) in place (lower), write its inverse to
+// Dinv (ld 64, stride sD) and, if Linv != nullptr, into Linv at (j, j).
+void potrf_diag(hipStream_t st, double* A, int lda, long long sA, int j, int jb, double* Dinv,
+                long long sD, double* Linv, int ldl, long long sL, DevInfo* info, int pass,
+                int batch);
+
+void copy_row(hipStream_t st, const double* src, int lds_, long long sS, double* dst, int ldd,
+              long long sD, int count, int batch);
+
+void schur_mblocks(hipStream_t st, int nblk, const int32_t* desc, const double* P, int ldp,
+                   long long sP, int cbase, int mg, double* Mbuf);
+void schur_avec(hipStream_t st, int nE, const int32_t* desc, const double* P, int ldp, long long sP,
+                int cbase, int acol, int mg, double* abuf);
+void schur_sblocks(hipStream_t st, int nE, int mg, const int32_t* tptr, const int32_t* tdesc,
+                   const int32_t* mptr, const int32_t* mdesc, const double* P, int ldp,
+                   long long sP, const double* Mbuf, double* S, int lds_);
+void schur_rhs(hipStream_t st, int nE, int mg, const int32_t* qdesc, const int32_t* gptr,
+               const int32_t* gdesc, const double* P, int ldp, long long sP, int qcol,
+               const double* Mbuf, const double* abuf, double* rhs, int inc);
+
+void trsv_lower_t_step(hipStream_t st, const double* L, int ld, int j0, int jb, const double* Dinv,
+                       double* y, double* u);
+
+void local_backsolve(hipStream_t st, int N, int n, int kpad, const double* X, int ldx, long long sX,
+                     int mI, int hrow, const int32_t* gidx, const double* u,
+                     const double* Linv1, const double* Linv2, const double* Linv3, int ldg,
+                     long long sG, double* c);
+
+void eval_points(hipStream_t st, int npts, const double* xy, int nx, int ny, double x0, double x1,
+                 double y0, double y1, int n, const double* W, const double* b, const double* c,
+                 double* u);
+
+constexpr int NB = 64;  // block size of the blocked Cholesky
+
+// Blocked right-looking Cholesky of a batch of (Mrows x n) lower trapezoids
+// (Mrows = n or n + 1; an extra last row r becomes r L^{-T}).  Writes the
+// inverses of the 64 x 64 diagonal blocks to Dinv (stride sD per matrix) and,
+// if Linv != nullptr, the inverse factor L^{-1} (strictly upper part untouched).
+void blocked_potrf(hipStream_t st, double* A, int lda, long long sA, int Mrows, int n, double* Dinv,
+                   long long sD, double* Linv, int ldl, long long sL, double* Tbuf, DevInfo* info,
+                   int pass, int batch);
+
+void init_info(hipStream_t st, DevInfo* info);
+void check_finite(hipStream_t st, const double* v, long long count, DevInfo* info);
+
+}  // namespace elmddm

@@ -1,0 +1,42 @@
+// Blocked factorisation drivers built from the batched kernels.
+#include <algorithm>
+
+#include "internal.h"
+
+namespace elmddm {
+
+// Blocked right-looking Cholesky of a batch of (Mrows x n) lower trapezoids
+// (Mrows = n or n + 1; an extra last row r is turned into r L^{-T}).  Writes
+// the inverses of the 64 x 64 diagonal blocks to Dinv and, if Linv is given,
+// the full inverse factor L^{-1} (strictly upper part left untouched).
+void blocked_potrf(hipStream_t st, double* A, int lda, long long sA, int Mrows, int n, double* Dinv,
+                   long long sD, double* Linv, int ldl, long long sL, double* Tbuf, DevInfo* info,
+                   int pass, int batch)
+{
+    for (int j = 0; j < n; j += NB) {
+        const int jb = std::min(NB, n - j);
+        double* Dj = Dinv + (long long)(j / NB) * NB * NB;
+        potrf_diag(st, A, lda, sA, j, jb, Dj, sD, Linv, ldl, sL, info, pass, batch);
+        const int Mb = Mrows - j - jb;
+        if (Mb > 0) {
+            double* panel = A + (long long)j * lda + (j + jb);
+            gemm_f64(st, false, true, 0, false, Mb, jb, jb, 1.0, panel, lda, sA, Dj, NB, sD, 0.0,
+                     panel, lda, sA, batch);
+            const int Nt = n - j - jb;
+            if (Nt > 0)
+                gemm_f64(st, false, true, 0, true, Mb, Nt, jb, -1.0, panel, lda, sA, panel, lda, sA,
+                         1.0, A + (long long)(j + jb) * lda + (j + jb), lda, sA, batch);
+        }
+    }
+    if (!Linv) return;
+    // L^{-1}, block row by block row: Linv[I, 0:i] = -Dinv_I (L[I, 0:i] Linv[0:i, 0:i]).
+    for (int i = NB; i < n; i += NB) {
+        const int ib = std::min(NB, n - i);
+        gemm_f64(st, false, false, 1, false, ib, i, i, 1.0, A + i, lda, sA, Linv, ldl, sL, 0.0, Tbuf,
+                 NB, (long long)NB * n, batch);
+        gemm_f64(st, false, false, 0, false, ib, i, ib, -1.0, Dinv + (long long)(i / NB) * NB * NB,
+                 NB, sD, Tbuf, NB, (long long)NB * n, 0.0, Linv + i, ldl, sL, batch);
+    }
+}
+
+}  // namespace elmddm

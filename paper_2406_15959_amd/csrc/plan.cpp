@@ -1,0 +1,749 @@
+// Host side of the elmddm C ABI: problem validation, point layout, index maps
+// for the interface system, device workspace, and the solve pipeline.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/elmddm.h"
+#include "internal.h"
+
+using namespace elmddm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+elmddm_status fail(elmddm_status st, const std::string& msg)
+{
+    g_last_error = msg;
+    return st;
+}
+
+int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+struct EdgeOwner {
+    int s;     // subdomain
+    int slot;  // local interface slot of the edge's first point
+};
+
+}  // namespace
+
+struct elmddm_plan {
+    elmddm_problem p{};
+    int N = 0, n = 0, nx = 0, ny = 0, q2 = 0, mg = 0, mb = 0;
+    int maxb = 0, maxk = 0, max_rows = 0;
+    int mI = 0, kpad = 0, hrow = 0, dbase = 0, ldx = 0, gram_rows = 0, ldg = 0, ldp = 0;
+    int nG = 0, nE = 0, nblk = 0, nblkS = 0, lds = 0;
+    int64_t nB = 0;
+    long long sX = 0, sG = 0, sL = 0, sD = 0, sP = 0;
+    double hx = 0, hy = 0;
+
+    // host layout
+    std::vector<double> int_pts, bnd_pts, ifc_pts;  // interleaved (x, y)
+    std::vector<double> cx, cy;
+
+    // device memory
+    std::vector<void*> allocs;
+    uint64_t bytes = 0;
+    double *X0 = nullptr, *X1 = nullptr, *G = nullptr, *Linv[3] = {nullptr, nullptr, nullptr};
+    double *Dinv = nullptr, *Tbuf = nullptr, *P = nullptr, *Mbuf = nullptr, *abuf = nullptr;
+    double *Sx = nullptr, *Skeep = nullptr, *DinvS = nullptr, *yvec = nullptr;
+    double *d_rx = nullptr, *d_ry = nullptr, *d_rnx = nullptr, *d_rny = nullptr;
+    double *d_cx = nullptr, *d_cy = nullptr;
+    int32_t *d_kind = nullptr, *d_src = nullptr, *d_cmap = nullptr, *d_gidx = nullptr;
+    int32_t *d_mdesc = nullptr, *d_adesc = nullptr, *d_tptr = nullptr, *d_tdesc = nullptr;
+    int32_t *d_mptr = nullptr, *d_mlist = nullptr, *d_qdesc = nullptr, *d_gptr = nullptr;
+    int32_t *d_gdesc = nullptr;
+    int n_mblocks = 0;
+    DevInfo* d_info = nullptr;
+    bool keep_schur = false;
+    bool schur_valid = false;
+    hipStream_t last_stream = nullptr;
+    bool solved = false;
+    // stage timing
+    bool timing = false;
+    hipEvent_t ev[ELMDDM_NUM_STAGES + 1] = {};
+    hipEvent_t pev[10] = {};  // per-pass Gram / Cholesky / triangular-solve boundaries
+    bool ev_ready = false;
+    bool ev_pending = false;
+    double stage_ms[ELMDDM_NUM_STAGES] = {};
+    int timed_solves = 0;
+
+    template <class T>
+    elmddm_status dalloc(T** ptr, size_t count)
+    {
+        *ptr = nullptr;
+        if (count == 0) count = 1;
+        void* q = nullptr;
+        if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(ELMDDM_OOM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+        }
+        allocs.push_back(q);
+        bytes += count * sizeof(T);
+        *ptr = static_cast<T*>(q);
+        return ELMDDM_OK;
+    }
+
+    template <class T>
+    elmddm_status upload(T** ptr, const std::vector<T>& v)
+    {
+        elmddm_status st = dalloc(ptr, v.size());
+        if (st != ELMDDM_OK) return st;
+        if (!v.empty() && hipMemcpy(*ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+            return fail(ELMDDM_HIP_ERROR, "hipMemcpy failed during plan creation");
+        return ELMDDM_OK;
+    }
+
+    void mark(int i, hipStream_t st)
+    {
+        if (timing) (void)hipEventRecord(ev[i], st);
+    }
+
+    // Fold the events of the previous timed solve into the totals.
+    void harvest()
+    {
+        if (!ev_pending) return;
+        (void)hipEventSynchronize(ev[ELMDDM_NUM_STAGES]);
+        auto el = [](hipEvent_t a, hipEvent_t b) {
+            float ms = 0.f;
+            return hipEventElapsedTime(&ms, a, b) == hipSuccess ? (double)ms : 0.0;
+        };
+        stage_ms[0] += el(ev[0], ev[1]);
+        for (int p = 0; p < 3; ++p) {
+            stage_ms[1] += el(pev[3 * p], pev[3 * p + 1]);
+            stage_ms[2] += el(pev[3 * p + 1], pev[3 * p + 2]);
+            stage_ms[3] += el(pev[3 * p + 2], p < 2 ? pev[3 * p + 3] : pev[9]);
+        }
+        stage_ms[3] += el(pev[9], ev[4]);
+        for (int i = 4; i < ELMDDM_NUM_STAGES; ++i) stage_ms[i] += el(ev[i], ev[i + 1]);
+        ++timed_solves;
+        ev_pending = false;
+    }
+
+    ~elmddm_plan()
+    {
+        if (ev_ready)
+            {
+            for (auto& e : ev) (void)hipEventDestroy(e);
+            for (auto& e : pev) (void)hipEventDestroy(e);
+        }
+        for (void* q : allocs) (void)hipFree(q);
+    }
+};
+
+namespace {
+
+elmddm_status validate(const elmddm_problem* p)
+{
+    if (!p) return fail(ELMDDM_INVALID_ARG, "problem is NULL");
+    if (!(p->x1 > p->x0) || !(p->y1 > p->y0) || !std::isfinite(p->x0) || !std::isfinite(p->x1) ||
+        !std::isfinite(p->y0) || !std::isfinite(p->y1))
+        return fail(ELMDDM_INVALID_ARG, "domain must be a finite rectangle with x1 > x0, y1 > y0");
+    if (p->nsub_x < 1 || p->nsub_y < 1 || p->nsub_x > 4096 || p->nsub_y > 4096)
+        return fail(ELMDDM_INVALID_ARG, "nsub_x, nsub_y must be in [1, 4096]");
+    if (p->neurons < 1 || p->neurons > 1024)
+        return fail(ELMDDM_INVALID_ARG, "neurons must be in [1, 1024]");
+    if (p->q_x < 1 || p->q_y < 1 || p->m_bdry_edge < 1 || p->m_ifc_edge < 1)
+        return fail(ELMDDM_INVALID_ARG, "point counts must be positive");
+    if (p->m_ifc_edge > 64) return fail(ELMDDM_UNSUPPORTED, "m_ifc_edge > 64 is not supported");
+    if ((int64_t)p->q_x * p->q_y < p->neurons)
+        return fail(ELMDDM_INVALID_ARG,
+                    "q_x*q_y must be >= neurons (full column rank needs m_i >= n_N, Section 3)");
+    if ((int64_t)p->q_x * p->q_y > (1 << 22)) return fail(ELMDDM_INVALID_ARG, "too many interior points");
+    if (p->op != ELMDDM_OP_POISSON && p->op != ELMDDM_OP_VARCOEF)
+        return fail(ELMDDM_INVALID_ARG, "unknown operator");
+    return ELMDDM_OK;
+}
+
+void edge_points(double p0x, double p0y, double p1x, double p1y, int m, std::vector<double>& out)
+{
+    for (int k = 0; k < m; ++k) {
+        const double t = ((double)k + 0.5) / (double)m;
+        out.push_back(p0x + t * (p1x - p0x));
+        out.push_back(p0y + t * (p1y - p0y));
+    }
+}
+
+elmddm_status build(elmddm_plan* P)
+{
+    const elmddm_problem& p = P->p;
+    const int nx = p.nsub_x, ny = p.nsub_y;
+    P->nx = nx;
+    P->ny = ny;
+    P->N = nx * ny;
+    P->n = p.neurons;
+    P->q2 = p.q_x * p.q_y;
+    P->mg = p.m_ifc_edge;
+    P->mb = p.m_bdry_edge;
+    P->hx = (p.x1 - p.x0) / nx;
+    P->hy = (p.y1 - p.y0) / ny;
+    const double hx = P->hx, hy = P->hy;
+    auto xline = [&](int i) { return p.x0 + i * hx; };
+    auto yline = [&](int j) { return p.y0 + j * hy; };
+    const int mg = P->mg, mb = P->mb, N = P->N, n = P->n;
+
+    // interface edges: vertical (edge row outer, x inner), then horizontal
+    const int nV = (nx - 1) * ny, nH = nx * (ny - 1);
+    P->nE = nV + nH;
+    P->nG = P->nE * mg;
+    auto vid = [&](int i, int j) { return j * (nx - 1) + (i - 1); };
+    auto hid = [&](int i, int j) { return nV + (j - 1) * nx + i; };
+    P->ifc_pts.clear();
+    for (int j = 0; j < ny; ++j)
+        for (int i = 1; i < nx; ++i) edge_points(xline(i), yline(j), xline(i), yline(j + 1), mg, P->ifc_pts);
+    for (int j = 1; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) edge_points(xline(i), yline(j), xline(i + 1), yline(j), mg, P->ifc_pts);
+
+    // per-subdomain edges
+    static const double NRM[4][2] = {{0, -1}, {1, 0}, {0, 1}, {-1, 0}};
+    std::vector<std::vector<std::pair<int, int>>> sub_edges(N);  // (edge, slot)
+    std::vector<std::vector<EdgeOwner>> owners(P->nE);
+    std::vector<int> nbnd(N, 0), nifc(N, 0);
+    P->cx.assign(N, 0.0);
+    P->cy.assign(N, 0.0);
+    struct SubPts {
+        std::vector<double> bnd, ifc, nrm;
+        std::vector<int> gidx;
+    };
+    std::vector<SubPts> sp(N);
+    P->int_pts.clear();
+    P->bnd_pts.clear();
+    for (int sy = 0; sy < ny; ++sy)
+        for (int sx = 0; sx < nx; ++sx) {
+            const int s = sy * nx + sx;
+            const double xa = xline(sx), ya = yline(sy), xb = xline(sx + 1), yb = yline(sy + 1);
+            P->cx[s] = xa + 0.5 * hx;
+            P->cy[s] = ya + 0.5 * hy;
+            for (int iy = 0; iy < p.q_y; ++iy)
+                for (int ix = 0; ix < p.q_x; ++ix) {
+                    const double tx = ((double)ix + 0.5) / (double)p.q_x;
+                    const double ty = ((double)iy + 0.5) / (double)p.q_y;
+                    P->int_pts.push_back(xa + tx * hx);
+                    P->int_pts.push_back(ya + ty * hy);
+                }
+            struct E {
+                double p0x, p0y, p1x, p1y;
+                bool ext;
+                int id;
+            } edges[4] = {
+                {xa, ya, xb, ya, sy == 0, sy == 0 ? -1 : hid(sx, sy)},
+                {xb, ya, xb, yb, sx == nx - 1, sx == nx - 1 ? -1 : vid(sx + 1, sy)},
+                {xa, yb, xb, yb, sy == ny - 1, sy == ny - 1 ? -1 : hid(sx, sy + 1)},
+                {xa, ya, xa, yb, sx == 0, sx == 0 ? -1 : vid(sx, sy)},
+            };
+            for (int e = 0; e < 4; ++e) {
+                if (edges[e].ext) {
+                    edge_points(edges[e].p0x, edges[e].p0y, edges[e].p1x, edges[e].p1y, mb, sp[s].bnd);
+                } else {
+                    const int id = edges[e].id;
+                    const int slot = (int)sp[s].gidx.size();
+                    sub_edges[s].push_back({id, slot});
+                    owners[id].push_back({s, slot});
+                    for (int k = 0; k < mg; ++k) {
+                        const int gi = id * mg + k;
+                        sp[s].gidx.push_back(gi);
+                        sp[s].ifc.push_back(P->ifc_pts[2 * gi]);
+                        sp[s].ifc.push_back(P->ifc_pts[2 * gi + 1]);
+                        sp[s].nrm.push_back(NRM[e][0]);
+                        sp[s].nrm.push_back(NRM[e][1]);
+                    }
+                }
+            }
+            nbnd[s] = (int)sp[s].bnd.size() / 2;
+            nifc[s] = (int)sp[s].gidx.size();
+            P->bnd_pts.insert(P->bnd_pts.end(), sp[s].bnd.begin(), sp[s].bnd.end());
+        }
+    P->nB = (int64_t)P->bnd_pts.size() / 2;
+    P->maxb = *std::max_element(nbnd.begin(), nbnd.end());
+    P->maxk = *std::max_element(nifc.begin(), nifc.end());
+    P->max_rows = 0;
+    for (int s = 0; s < N; ++s) P->max_rows = std::max(P->max_rows, P->q2 + nbnd[s] + nifc[s]);
+
+    // X row layout per subdomain:
+    // [0, mI) interior + boundary (+ zero pad) | [mI, mI+kpad) interface values |
+    // [hrow, hrow+16) h row + pad | [dbase, dbase+kpad) flux rows
+    P->mI = round_up(P->q2 + P->maxb, 16);
+    P->kpad = round_up(P->maxk, 16);
+    P->hrow = P->mI + P->kpad;
+    P->dbase = P->hrow + 16;
+    P->ldx = P->dbase + P->kpad;
+    P->gram_rows = P->mI + P->kpad;
+    P->ldg = round_up(n + 1, 16);
+    P->ldp = 2 * P->kpad + 16;
+    P->nblk = (n + NB - 1) / NB;
+    P->nblkS = (P->nG + NB - 1) / NB;
+    P->lds = P->nG + 1;
+    P->sX = (long long)P->ldx * (n + 1);
+    P->sG = (long long)P->ldg * (n + 1);
+    P->sL = (long long)P->ldg * n;
+    P->sD = (long long)P->nblk * NB * NB;
+    P->sP = (long long)P->ldp * (P->kpad + 1);
+
+    const int ldx = P->ldx;
+    std::vector<double> rx((size_t)N * ldx, 0.0), ry((size_t)N * ldx, 0.0), rnx((size_t)N * ldx, 0.0),
+        rny((size_t)N * ldx, 0.0);
+    std::vector<int32_t> kind((size_t)N * ldx, ROW_ZERO), src((size_t)N * ldx, 0),
+        cmap((size_t)N * ldx, -1), gidx((size_t)N * std::max(P->kpad, 1), -1);
+    int64_t bcount = 0;
+    for (int s = 0; s < N; ++s) {
+        const size_t base = (size_t)s * ldx;
+        for (int i = 0; i < P->q2; ++i) {
+            rx[base + i] = P->int_pts[2 * ((size_t)s * P->q2 + i)];
+            ry[base + i] = P->int_pts[2 * ((size_t)s * P->q2 + i) + 1];
+            kind[base + i] = ROW_INTERIOR;
+            src[base + i] = s * P->q2 + i;
+            cmap[base + i] = i;
+        }
+        for (int i = 0; i < nbnd[s]; ++i) {
+            const size_t r = base + P->q2 + i;
+            rx[r] = sp[s].bnd[2 * i];
+            ry[r] = sp[s].bnd[2 * i + 1];
+            kind[r] = ROW_BOUNDARY;
+            src[r] = (int32_t)(bcount + i);
+            cmap[r] = P->q2 + i;
+        }
+        bcount += nbnd[s];
+        for (int i = 0; i < nifc[s]; ++i) {
+            size_t r = base + P->mI + i;
+            rx[r] = sp[s].ifc[2 * i];
+            ry[r] = sp[s].ifc[2 * i + 1];
+            kind[r] = ROW_IFC_VALUE;
+            cmap[r] = P->q2 + nbnd[s] + i;
+            r = base + P->dbase + i;
+            rx[r] = sp[s].ifc[2 * i];
+            ry[r] = sp[s].ifc[2 * i + 1];
+            rnx[r] = sp[s].nrm[2 * i];
+            rny[r] = sp[s].nrm[2 * i + 1];
+            kind[r] = ROW_FLUX;
+            cmap[r] = -2 - i;
+            gidx[(size_t)s * P->kpad + i] = sp[s].gidx[i];
+        }
+    }
+
+    // Interface system index structures.
+    // adjacency of a flux edge g: all interface edges of its two owners
+    std::vector<std::vector<int>> adj(P->nE);
+    for (int g = 0; g < P->nE; ++g) {
+        for (const EdgeOwner& o : owners[g])
+            for (auto& es : sub_edges[o.s]) adj[g].push_back(es.first);
+        std::sort(adj[g].begin(), adj[g].end());
+        adj[g].erase(std::unique(adj[g].begin(), adj[g].end()), adj[g].end());
+    }
+    auto slot_of = [&](int s, int e) {
+        for (auto& es : sub_edges[s])
+            if (es.first == e) return es.second;
+        return -1;
+    };
+    std::vector<int32_t> mdesc, adesc, qdesc;
+    std::map<std::pair<int, int>, int> mid;
+    for (int g = 0; g < P->nE; ++g) {
+        for (int E : adj[g]) {
+            int32_t d[8] = {-1, 0, 0, -1, 0, 0, 0, 0};
+            int t = 0;
+            for (const EdgeOwner& o : owners[g]) {
+                const int se = slot_of(o.s, E);
+                if (se < 0) continue;
+                d[3 * t] = o.s;
+                d[3 * t + 1] = o.slot;
+                d[3 * t + 2] = se;
+                ++t;
+            }
+            mid[{g, E}] = (int)(mdesc.size() / 8);
+            mdesc.insert(mdesc.end(), d, d + 8);
+        }
+        int32_t a[4] = {-1, 0, -1, 0};
+        for (size_t t = 0; t < owners[g].size() && t < 2; ++t) {
+            a[2 * t] = owners[g][t].s;
+            a[2 * t + 1] = owners[g][t].slot;
+        }
+        adesc.insert(adesc.end(), a, a + 4);
+        qdesc.insert(qdesc.end(), a, a + 4);
+    }
+    P->n_mblocks = (int)(mdesc.size() / 8);
+    const size_t nEE = (size_t)P->nE * P->nE;
+    std::vector<std::vector<int32_t>> tl(nEE), ml(nEE);
+    for (int s = 0; s < N; ++s)
+        for (auto& e1 : sub_edges[s])
+            for (auto& e2 : sub_edges[s]) {
+                const size_t blk = (size_t)e1.first + (size_t)e2.first * P->nE;
+                tl[blk].insert(tl[blk].end(), {s, e1.second, e2.second, e1.first == e2.first ? 1 : 0});
+            }
+    std::vector<std::vector<int32_t>> gl(P->nE);
+    for (int g = 0; g < P->nE; ++g)
+        for (int E1 : adj[g]) {
+            gl[E1].push_back(mid[{g, E1}]);
+            gl[E1].push_back(g);
+            for (int E2 : adj[g]) {
+                const size_t blk = (size_t)E1 + (size_t)E2 * P->nE;
+                ml[blk].push_back(mid[{g, E1}]);
+                ml[blk].push_back(mid[{g, E2}]);
+            }
+        }
+    std::vector<int32_t> tptr(nEE + 1, 0), mptr(nEE + 1, 0), tdesc, mlist, gptr(P->nE + 1, 0), gdesc;
+    for (size_t b = 0; b < nEE; ++b) {
+        tptr[b + 1] = tptr[b] + (int32_t)(tl[b].size() / 4);
+        mptr[b + 1] = mptr[b] + (int32_t)(ml[b].size() / 2);
+        tdesc.insert(tdesc.end(), tl[b].begin(), tl[b].end());
+        mlist.insert(mlist.end(), ml[b].begin(), ml[b].end());
+    }
+    for (int e = 0; e < P->nE; ++e) {
+        gptr[e + 1] = gptr[e] + (int32_t)(gl[e].size() / 2);
+        gdesc.insert(gdesc.end(), gl[e].begin(), gl[e].end());
+    }
+
+    // ---- device allocations ----
+    elmddm_status st;
+#define TRY(x)                       \
+    do {                             \
+        st = (x);                    \
+        if (st != ELMDDM_OK) return st; \
+    } while (0)
+    TRY(P->upload(&P->d_rx, rx));
+    TRY(P->upload(&P->d_ry, ry));
+    TRY(P->upload(&P->d_rnx, rnx));
+    TRY(P->upload(&P->d_rny, rny));
+    TRY(P->upload(&P->d_kind, kind));
+    TRY(P->upload(&P->d_src, src));
+    TRY(P->upload(&P->d_cmap, cmap));
+    TRY(P->upload(&P->d_gidx, gidx));
+    TRY(P->upload(&P->d_cx, P->cx));
+    TRY(P->upload(&P->d_cy, P->cy));
+    TRY(P->upload(&P->d_mdesc, mdesc));
+    TRY(P->upload(&P->d_adesc, adesc));
+    TRY(P->upload(&P->d_qdesc, qdesc));
+    TRY(P->upload(&P->d_tptr, tptr));
+    TRY(P->upload(&P->d_tdesc, tdesc));
+    TRY(P->upload(&P->d_mptr, mptr));
+    TRY(P->upload(&P->d_mlist, mlist));
+    TRY(P->upload(&P->d_gptr, gptr));
+    TRY(P->upload(&P->d_gdesc, gdesc));
+    TRY(P->dalloc(&P->X0, (size_t)N * P->sX));
+    TRY(P->dalloc(&P->X1, (size_t)N * P->sX));
+    TRY(P->dalloc(&P->G, (size_t)N * P->sG));
+    for (int i = 0; i < 3; ++i) TRY(P->dalloc(&P->Linv[i], (size_t)N * P->sL));
+    TRY(P->dalloc(&P->Dinv, (size_t)N * P->sD));
+    TRY(P->dalloc(&P->Tbuf, (size_t)N * NB * n));
+    TRY(P->dalloc(&P->P, (size_t)N * P->sP));
+    TRY(P->dalloc(&P->Mbuf, (size_t)std::max(P->n_mblocks, 1) * mg * mg));
+    TRY(P->dalloc(&P->abuf, (size_t)std::max(P->nE, 1) * mg));
+    TRY(P->dalloc(&P->Sx, (size_t)P->lds * std::max(P->nG, 1)));
+    TRY(P->dalloc(&P->DinvS, (size_t)std::max(P->nblkS, 1) * NB * NB));
+    TRY(P->dalloc(&P->yvec, (size_t)std::max(P->nG, 1)));
+    TRY(P->dalloc(&P->d_info, 1));
+    // The strictly upper parts of the inverse factors are never written by the
+    // solve and must read as zero.
+    for (int i = 0; i < 3; ++i)
+        if (hipMemset(P->Linv[i], 0, (size_t)N * P->sL * sizeof(double)) != hipSuccess)
+            return fail(ELMDDM_HIP_ERROR, "hipMemset failed during plan creation");
+    if (hipMemset(P->X1, 0, (size_t)N * P->sX * sizeof(double)) != hipSuccess)
+        return fail(ELMDDM_HIP_ERROR, "hipMemset failed during plan creation");
+#undef TRY
+    return ELMDDM_OK;
+}
+
+RowTable row_table(const elmddm_plan* P)
+{
+    RowTable t;
+    t.x = P->d_rx;
+    t.y = P->d_ry;
+    t.nx = P->d_rnx;
+    t.ny = P->d_rny;
+    t.kind = P->d_kind;
+    t.src = P->d_src;
+    t.cmap = P->d_cmap;
+    return t;
+}
+
+SubGeom sub_geom(const elmddm_plan* P)
+{
+    SubGeom g;
+    g.cx = P->d_cx;
+    g.cy = P->d_cy;
+    g.sx = 2.0 / P->hx;
+    g.sy = 2.0 / P->hy;
+    return g;
+}
+
+elmddm_status check_launch(const char* where)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(ELMDDM_HIP_ERROR, std::string(where) + ": " + hipGetErrorString(e));
+    return ELMDDM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+elmddm_status elmddm_plan_create(const elmddm_problem* problem, elmddm_plan** plan)
+{
+    if (!plan) return fail(ELMDDM_INVALID_ARG, "plan output pointer is NULL");
+    *plan = nullptr;
+    elmddm_status st = validate(problem);
+    if (st != ELMDDM_OK) return st;
+    elmddm_plan* P = new (std::nothrow) elmddm_plan();
+    if (!P) return fail(ELMDDM_OOM, "host allocation failed");
+    P->p = *problem;
+    try {
+        st = build(P);
+    } catch (const std::bad_alloc&) {
+        st = fail(ELMDDM_OOM, "host allocation failed while building the layout");
+    }
+    if (st != ELMDDM_OK) {
+        delete P;
+        return st;
+    }
+    *plan = P;
+    return ELMDDM_OK;
+}
+
+elmddm_status elmddm_plan_destroy(elmddm_plan* plan)
+{
+    if (plan) {
+        if (plan->last_stream) (void)hipStreamSynchronize(plan->last_stream);
+        delete plan;
+    }
+    return ELMDDM_OK;
+}
+
+elmddm_status elmddm_plan_sizes(const elmddm_plan* P, elmddm_sizes* s)
+{
+    if (!P || !s) return fail(ELMDDM_INVALID_ARG, "NULL argument");
+    s->nsub = P->N;
+    s->neurons = P->n;
+    s->n_interior = P->q2;
+    s->n_interface = P->nG;
+    s->n_boundary = P->nB;
+    s->max_rows = P->max_rows;
+    s->max_ifc = P->maxk;
+    s->device_bytes = P->bytes;
+    return ELMDDM_OK;
+}
+
+elmddm_status elmddm_points(const elmddm_plan* P, int32_t kind, double* xy, int64_t capacity)
+{
+    if (!P || !xy) return fail(ELMDDM_INVALID_ARG, "NULL argument");
+    const std::vector<double>* v = nullptr;
+    if (kind == ELMDDM_POINTS_INTERIOR) v = &P->int_pts;
+    else if (kind == ELMDDM_POINTS_BOUNDARY) v = &P->bnd_pts;
+    else if (kind == ELMDDM_POINTS_INTERFACE) v = &P->ifc_pts;
+    else return fail(ELMDDM_INVALID_ARG, "unknown point kind");
+    if (capacity < (int64_t)(v->size() / 2)) return fail(ELMDDM_INVALID_ARG, "capacity too small");
+    std::memcpy(xy, v->data(), v->size() * sizeof(double));
+    return ELMDDM_OK;
+}
+
+elmddm_status elmddm_assemble(elmddm_plan* P, const double* W, const double* b, const double* f,
+                              const double* g, const double* coef, double* K, double* A, double* F,
+                              void* stream)
+{
+    if (!P || !W || !b || !f || !K || !A || !F) return fail(ELMDDM_INVALID_ARG, "NULL argument");
+    if (P->nB > 0 && !g) return fail(ELMDDM_INVALID_ARG, "g is NULL but the problem has boundary points");
+    if (P->p.op == ELMDDM_OP_VARCOEF && !coef) return fail(ELMDDM_INVALID_ARG, "coef is NULL for VARCOEF");
+    hipStream_t st = (hipStream_t)stream;
+    assemble(st, P->N, P->ldx, P->n, row_table(P), sub_geom(P), P->p.op, W, b, f, g, coef, P->q2,
+             nullptr, F, P->max_rows, K, P->max_rows, A, std::max(P->maxk, 1));
+    return check_launch("assemble");
+}
+
+elmddm_status elmddm_plan_keep_schur(elmddm_plan* P, int32_t keep)
+{
+    if (!P) return fail(ELMDDM_INVALID_ARG, "NULL plan");
+    if (keep && !P->Skeep) {
+        elmddm_status st = P->dalloc(&P->Skeep, (size_t)P->lds * std::max(P->nG, 1));
+        if (st != ELMDDM_OK) return st;
+    }
+    P->keep_schur = keep != 0;
+    return ELMDDM_OK;
+}
+
+elmddm_status elmddm_get_schur(elmddm_plan* P, double* S, double* rhs, void* stream)
+{
+    if (!P || !S || !rhs) return fail(ELMDDM_INVALID_ARG, "NULL argument");
+    if (!P->schur_valid) return fail(ELMDDM_INVALID_ARG, "no Schur system kept (call elmddm_plan_keep_schur before solving)");
+    hipStream_t st = (hipStream_t)stream;
+    if (P->nG == 0) return ELMDDM_OK;
+    // S: the first nG rows of each column; rhs: row nG.
+    if (hipMemcpy2DAsync(S, (size_t)P->nG * sizeof(double), P->Skeep, (size_t)P->lds * sizeof(double),
+                         (size_t)P->nG * sizeof(double), P->nG, hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return check_launch("get_schur");
+    copy_row(st, P->Skeep + P->nG, P->lds, 0, rhs, 1, 0, P->nG, 1);
+    return check_launch("get_schur");
+}
+
+elmddm_status elmddm_solve(elmddm_plan* P, const double* W, const double* b, const double* f,
+                           const double* g, const double* coef, double* u_gamma, double* c,
+                           void* stream)
+{
+    if (!P || !W || !b || !f || !c) return fail(ELMDDM_INVALID_ARG, "NULL argument");
+    if (P->nB > 0 && !g) return fail(ELMDDM_INVALID_ARG, "g is NULL but the problem has boundary points");
+    if (P->nG > 0 && !u_gamma) return fail(ELMDDM_INVALID_ARG, "u_gamma is NULL");
+    if (P->p.op == ELMDDM_OP_VARCOEF && !coef) return fail(ELMDDM_INVALID_ARG, "coef is NULL for VARCOEF");
+    hipStream_t st = (hipStream_t)stream;
+    if (P->timing) P->harvest();
+    P->last_stream = st;
+    P->solved = true;
+    const int N = P->N, n = P->n, ldx = P->ldx, ldg = P->ldg;
+    init_info(st, P->d_info);
+    P->mark(0, st);
+
+    // Feature assembly: X0 = [K rows | interface rows | flux rows], column n = F.
+    assemble(st, N, ldx, n, row_table(P), sub_geom(P), P->p.op, W, b, f, g, coef, P->q2, P->X0,
+             nullptr, 0, nullptr, 0, nullptr, 0);
+    P->mark(1, st);
+
+    // Three-pass shifted CholeskyQR of every K^s (Fukaya et al., SIAM J. Sci.
+    // Comput. 42 (2020)); the flux rows ride along through the triangular
+    // solves but stay out of the Gram matrices.  Pass 1 shifts the Gram
+    // diagonal by s * diag(G) (column-scaled shift), pass 3 also factors the
+    // extra row F^T Q2, which becomes h = Q^T F.
+    const double u = 0x1p-53;
+    const double shift = 11.0 * ((double)P->gram_rows * n + (double)n * (n + 1)) * u * n;
+    double* src = P->X0;
+    double* dst = P->X1;
+    for (int pass = 1; pass <= 3; ++pass) {
+        const int ncol = pass == 3 ? n + 1 : n;
+        if (P->timing) (void)hipEventRecord(P->pev[3 * (pass - 1)], st);
+        gemm_f64(st, true, false, 0, true, ncol, ncol, P->gram_rows, 1.0, src, ldx, P->sX, src, ldx,
+                 P->sX, 0.0, P->G, ldg, P->sG, N);
+        if (P->timing) (void)hipEventRecord(P->pev[3 * (pass - 1) + 1], st);
+        if (pass == 1) scale_diag(st, P->G, ldg, P->sG, n, 1.0 + shift, N);
+        blocked_potrf(st, P->G, ldg, P->sG, ncol, n, P->Dinv, P->sD, P->Linv[pass - 1], ldg, P->sL,
+                      P->Tbuf, P->d_info, pass, N);
+        if (P->timing) (void)hipEventRecord(P->pev[3 * (pass - 1) + 2], st);
+        const int r0 = pass == 3 ? P->mI : 0;
+        gemm_f64(st, false, true, 2, false, ldx - r0, n, n, 1.0, src + r0, ldx, P->sX,
+                 P->Linv[pass - 1], ldg, P->sL, 0.0, dst + r0, ldx, P->sX, N);
+        if (pass < 3) std::swap(src, dst);
+    }
+    if (P->timing) (void)hipEventRecord(P->pev[9], st);
+    // dst (X1) now holds Q3 interface rows and Z^T = A R^{-1}; put h^T in its row.
+    copy_row(st, P->G + n, ldg, P->sG, dst + P->hrow, ldx, P->sX, n, N);
+    P->mark(4, st);
+    elmddm_status est = check_launch("local factorisation");
+    if (est != ELMDDM_OK) return est;
+
+    if (P->nG > 0) {
+        // P_s = [Y^T; h^T; Z^T] [Y h]  -> T_s, q_s, C_s, a_s
+        gemm_f64(st, false, true, 0, false, 2 * P->kpad + 16, P->kpad + 1, n, 1.0, dst + P->mI, ldx,
+                 P->sX, dst + P->mI, ldx, P->sX, 0.0, P->P, P->ldp, P->sP, N);
+        const int cbase = P->kpad + 16;
+        schur_mblocks(st, P->n_mblocks, P->d_mdesc, P->P, P->ldp, P->sP, cbase, P->mg, P->Mbuf);
+        schur_avec(st, P->nE, P->d_adesc, P->P, P->ldp, P->sP, cbase, P->kpad, P->mg, P->abuf);
+        schur_sblocks(st, P->nE, P->mg, P->d_tptr, P->d_tdesc, P->d_mptr, P->d_mlist, P->P, P->ldp,
+                      P->sP, P->Mbuf, P->Sx, P->lds);
+        schur_rhs(st, P->nE, P->mg, P->d_qdesc, P->d_gptr, P->d_gdesc, P->P, P->ldp, P->sP, P->kpad,
+                  P->Mbuf, P->abuf, P->Sx + P->nG, P->lds);
+        P->mark(5, st);
+        if (P->keep_schur && P->Skeep) {
+            (void)hipMemcpyAsync(P->Skeep, P->Sx, (size_t)P->lds * P->nG * sizeof(double),
+                                 hipMemcpyDeviceToDevice, st);
+            P->schur_valid = true;
+        }
+        // Interface solve: Cholesky of [S; rhs^T] gives L and y = L^{-1} rhs,
+        // then L^T u = y block by block.
+        blocked_potrf(st, P->Sx, P->lds, 0, P->nG + 1, P->nG, P->DinvS, 0, nullptr, 0, 0, nullptr,
+                      P->d_info, 4, 1);
+        copy_row(st, P->Sx + P->nG, P->lds, 0, P->yvec, 1, 0, P->nG, 1);
+        P->mark(6, st);
+        for (int jb0 = (P->nblkS - 1) * NB; jb0 >= 0; jb0 -= NB) {
+            const int jb = std::min(NB, P->nG - jb0);
+            trsv_lower_t_step(st, P->Sx, P->lds, jb0, jb, P->DinvS + (long long)(jb0 / NB) * NB * NB,
+                              P->yvec, u_gamma);
+        }
+        est = check_launch("interface solve");
+        if (est != ELMDDM_OK) return est;
+    } else {
+        P->mark(5, st);
+        P->mark(6, st);
+    }
+    P->mark(7, st);
+    local_backsolve(st, N, n, P->kpad, dst, ldx, P->sX, P->mI, P->hrow, P->d_gidx, u_gamma,
+                    P->Linv[0], P->Linv[1], P->Linv[2], ldg, P->sL, c);
+    const long long nc = (long long)N * n;
+    P->mark(8, st);
+    check_finite(st, c, nc, P->d_info);
+    if (P->nG > 0) check_finite(st, u_gamma, (long long)P->nG, P->d_info);
+    if (P->timing) P->ev_pending = true;
+    return check_launch("back-solve");
+}
+
+elmddm_status elmddm_solve_info(elmddm_plan* P, elmddm_info* info)
+{
+    if (!P || !info) return fail(ELMDDM_INVALID_ARG, "NULL argument");
+    if (!P->solved) return fail(ELMDDM_INVALID_ARG, "no solve has been enqueued on this plan");
+    if (hipStreamSynchronize(P->last_stream) != hipSuccess) return check_launch("solve_info sync");
+    DevInfo h{};
+    if (hipMemcpy(&h, P->d_info, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess)
+        return check_launch("solve_info copy");
+    info->status = h.status;
+    info->bad_subdomain = h.bad_subdomain == INT_MAX ? -1 : h.bad_subdomain;
+    info->bad_pass = h.bad_pass;
+    info->reserved = 0;
+    return ELMDDM_OK;
+}
+
+elmddm_status elmddm_eval(elmddm_plan* P, const double* W, const double* b, const double* c,
+                          const double* xy, int64_t npts, double* u, void* stream)
+{
+    if (!P || !W || !b || !c || (npts > 0 && (!xy || !u))) return fail(ELMDDM_INVALID_ARG, "NULL argument");
+    if (npts < 0 || npts > INT_MAX) return fail(ELMDDM_INVALID_ARG, "npts out of range");
+    eval_points((hipStream_t)stream, (int)npts, xy, P->nx, P->ny, P->p.x0, P->p.x1, P->p.y0, P->p.y1,
+                P->n, W, b, c, u);
+    return check_launch("eval");
+}
+
+elmddm_status elmddm_set_timing(elmddm_plan* P, int32_t enable)
+{
+    if (!P) return fail(ELMDDM_INVALID_ARG, "NULL plan");
+    if (enable && !P->ev_ready) {
+        for (auto& e : P->ev)
+            if (hipEventCreate(&e) != hipSuccess) return check_launch("hipEventCreate");
+        for (auto& e : P->pev)
+            if (hipEventCreate(&e) != hipSuccess) return check_launch("hipEventCreate");
+        P->ev_ready = true;
+    }
+    if (P->ev_pending && P->last_stream) (void)hipStreamSynchronize(P->last_stream);
+    P->ev_pending = false;
+    P->timing = enable != 0;
+    for (double& v : P->stage_ms) v = 0.0;
+    P->timed_solves = 0;
+    return ELMDDM_OK;
+}
+
+elmddm_status elmddm_stage_times(elmddm_plan* P, double* ms, int32_t* solves)
+{
+    if (!P || !ms) return fail(ELMDDM_INVALID_ARG, "NULL argument");
+    P->harvest();
+    for (int i = 0; i < ELMDDM_NUM_STAGES; ++i) ms[i] = P->stage_ms[i];
+    if (solves) *solves = P->timed_solves;
+    return ELMDDM_OK;
+}
+
+const char* elmddm_status_string(elmddm_status s)
+{
+    switch (s) {
+        case ELMDDM_OK: return "ok";
+        case ELMDDM_INVALID_ARG: return "invalid argument";
+        case ELMDDM_OOM: return "out of memory";
+        case ELMDDM_NOT_SPD: return "local Gram matrix not positive definite";
+        case ELMDDM_SCHUR_NOT_SPD: return "interface Schur matrix not positive definite";
+        case ELMDDM_NOT_CONVERGED: return "iteration did not converge";
+        case ELMDDM_NONFINITE: return "non-finite values in the result";
+        case ELMDDM_HIP_ERROR: return "HIP runtime error";
+        case ELMDDM_UNSUPPORTED: return "unsupported configuration";
+    }
+    return "unknown status";
+}
+
+const char* elmddm_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

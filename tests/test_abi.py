@@ -1,0 +1,68 @@
+"""The C-ABI library builds, loads and exports every declared symbol (CPU only)."""
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "elmddm.h")
+
+
+def _lib_path():
+    from paper_2406_15959_amd import binding
+    if not os.path.exists(binding._LIB_PATH):
+        from paper_2406_15959_amd import build
+        build.build_library()
+    return binding._LIB_PATH
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(elmddm_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = _lib_path()
+    out = subprocess.run(["nm", "-D", "--defined-only", lib], capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (elmddm_\w+)", out))
+    missing = [s for s in declared_symbols() if s not in exported]
+    assert not missing, missing
+    assert len(declared_symbols()) >= 12
+
+
+def test_binding_covers_the_header():
+    from paper_2406_15959_amd import binding
+    assert sorted(binding.EXPORTED) == declared_symbols()
+
+
+def test_library_loads_and_reports_status_strings():
+    _lib_path()
+    from paper_2406_15959_amd import binding as B
+    L = B.lib()
+    assert L.elmddm_status_string(B.OK) == b"ok"
+    assert b"positive definite" in L.elmddm_status_string(B.NOT_SPD)
+
+
+@pytest.mark.parametrize("field,value", [("neurons", 0), ("q_x", 0), ("nsub_x", 0), ("m_ifc_edge", 0),
+                                         ("op", 7), ("x1", -1.0), ("m_ifc_edge", 65)])
+def test_plan_create_rejects_bad_problems_without_a_gpu(field, value):
+    """Validation happens on the host before any device call."""
+    _lib_path()
+    from paper_2406_15959_amd import binding as B
+    p = B.make_problem(nsub_x=2, nsub_y=2, neurons=10, q_x=4, q_y=4, m_bdry_edge=3, m_ifc_edge=3)
+    setattr(p, field, value)
+    with pytest.raises(B.ElmddmError) as e:
+        B.Plan(p)
+    assert e.value.status in (B.INVALID_ARG, B.UNSUPPORTED)
+
+
+def test_plan_create_rejects_too_few_interior_points():
+    """The Proposition of Section 3 needs m_i >= n_N per subdomain."""
+    _lib_path()
+    from paper_2406_15959_amd import binding as B
+    p = B.make_problem(nsub_x=2, nsub_y=2, neurons=17, q_x=4, q_y=4, m_bdry_edge=3, m_ifc_edge=3)
+    with pytest.raises(B.ElmddmError) as e:
+        B.Plan(p)
+    assert e.value.status == B.INVALID_ARG
+    assert b"neurons" in B.lib().elmddm_last_error()

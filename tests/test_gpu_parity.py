@@ -1,0 +1,144 @@
+"""End-to-end parity of the HIP path (through the C ABI) with the FP64 oracle."""
+import numpy as np
+import pytest
+
+import workload as wl
+from gpu_helpers import gpu_solve, oracle_solve, to_c_problem
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP64 = 1e-8   # relative L2 of u_Gamma and u_h against the oracle, plain FP64 mode
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def test_points_match_oracle_layout(gpu):
+    from oracle.layout import build_layout
+    from paper_2406_15959_amd import binding as B
+    for P in [wl.CONFIG_SMALL, wl.Problem(3, 2, 20, 5, 7, 3, 4, R=1.0)]:
+        plan = B.Plan(to_c_problem(P))
+        lay = build_layout(P)
+        assert np.array_equal(plan.points(B.POINTS_INTERIOR), lay.interior_points())
+        assert np.array_equal(plan.points(B.POINTS_BOUNDARY), lay.boundary_points())
+        assert np.array_equal(plan.points(B.POINTS_INTERFACE), lay.interface_points)
+        assert plan.sizes.n_interface == lay.n_interface
+
+
+@pytest.mark.parametrize("P", [wl.CONFIG_SMALL, wl.Problem(3, 2, 50, 9, 8, 5, 7, op=wl.OP_VARCOEF, R=1.5, k1=2, k2=1)])
+def test_assembly_matches_oracle_blocks(gpu, P):
+    import torch
+    from oracle import ddm
+    from oracle.layout import build_layout
+    from paper_2406_15959_amd import binding as B
+    plan = B.Plan(to_c_problem(P))
+    s = plan.sizes
+    W, b = wl.hidden_params(P, 3)
+    f, g, coef = wl.sample_data(P, plan.points(B.POINTS_INTERIOR), plan.points(B.POINTS_BOUNDARY))
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    K = torch.zeros(s.nsub * s.neurons * s.max_rows, dtype=torch.float64, device="cuda")
+    A = torch.zeros(s.nsub * s.neurons * max(s.max_ifc, 1), dtype=torch.float64, device="cuda")
+    F = torch.zeros(s.nsub * s.max_rows, dtype=torch.float64, device="cuda")
+    plan.assemble(t(W), t(b), t(f), t(g), t(coef) if coef is not None else None, K, A, F)
+    torch.cuda.synchronize()
+    Kg = K.cpu().numpy().reshape(s.nsub, s.neurons, s.max_rows)
+    Ag = A.cpu().numpy().reshape(s.nsub, s.neurons, max(s.max_ifc, 1))
+    Fg = F.cpu().numpy().reshape(s.nsub, s.max_rows)
+    lay = build_layout(P)
+    data = ddm.problem_data(P, lay, wl.source_f, wl.boundary_g, wl.coefficient)
+    for si, sub in enumerate(lay.subs):
+        blk = ddm.assemble_local(P, sub, W[si], b[si], *data[si])
+        m, k = blk.K.shape[0], blk.n_ifc
+        assert np.abs(Kg[si, :, :m].T - blk.K).max() <= 1e-13 * np.abs(blk.K).max()
+        assert np.abs(Kg[si, :, m:]).max(initial=0) == 0.0
+        if k:
+            assert np.abs(Ag[si, :, :k].T - blk.D).max() <= 1e-13 * np.abs(blk.D).max()
+        assert np.abs(Fg[si, :m] - blk.F).max() <= 1e-14 * np.abs(blk.F).max()
+
+
+CASES = [
+    ("small-2x2", wl.CONFIG_SMALL, 1000),
+    ("strip-3x1", wl.Problem(3, 1, 30, 8, 8, 6, 5, R=1.5), 5),
+    ("strip-1x2", wl.Problem(1, 2, 40, 9, 7, 6, 9, R=1.5), 6),
+    ("ragged-3x2-varcoef", wl.Problem(3, 2, 70, 11, 9, 10, 13, op=wl.OP_VARCOEF, R=2.0, k1=1, k2=3), 7),
+    ("single-1x1", wl.Problem(1, 1, 90, 12, 12, 11, 4, R=2.0), 8),
+    ("4x3-n130", wl.Problem(4, 3, 130, 13, 12, 12, 17, R=2.5), 9),
+]
+
+
+@pytest.mark.parametrize("name,P,seed", CASES, ids=[c[0] for c in CASES])
+def test_solve_matches_oracle(gpu, name, P, seed):
+    g = gpu_solve(P, seed)
+    o = oracle_solve(P, seed)
+    assert g["info"].status == 0, g["info"].status
+    if P.n_interface:
+        assert rel(g["u_gamma"], o["u_gamma"]) <= TOL_FP64
+    assert rel(g["uh"], o["uh"]) <= TOL_FP64
+
+
+def test_schur_system_matches_oracle(gpu):
+    P = wl.Problem(3, 3, 60, 10, 10, 8, 6, R=2.0)
+    g = gpu_solve(P, 21, keep_schur=True)
+    o = oracle_solve(P, 21)
+    S, rhs = o["sol"].S, o["sol"].g
+    assert np.linalg.norm(g["S"] - S) <= 1e-9 * np.linalg.norm(S)
+    assert np.linalg.norm(g["rhs"] - rhs) <= 1e-9 * np.linalg.norm(rhs)
+
+
+def test_full_8x8_matches_oracle(gpu):
+    """The 8x8 workload at full size: 64 subdomains, 400 neurons, 40x40 points."""
+    P = wl.CONFIG_8x8
+    g = gpu_solve(P, 2000)
+    o = oracle_solve(P, 2000)
+    assert g["info"].status == 0
+    assert rel(g["u_gamma"], o["u_gamma"]) <= TOL_FP64
+    assert rel(g["uh"], o["uh"]) <= TOL_FP64
+    ex, ey = wl.eval_grid(P)
+    assert rel(g["uh"], wl.exact_u(P, ex, ey)) < 1e-4
+
+
+def test_duplicate_neurons_report_not_spd(gpu):
+    """Two identical neurons make K^s rank deficient: reported with the subdomain index."""
+    import torch
+    from paper_2406_15959_amd import binding as B
+    P = wl.Problem(2, 2, 40, 8, 8, 6, 6, R=2.0)
+    plan = B.Plan(to_c_problem(P))
+    s = plan.sizes
+    W, b = wl.hidden_params(P, 4)
+    W[2, 5] = W[2, 3]
+    b[2, 5] = b[2, 3]
+    f, g, _ = wl.sample_data(P, plan.points(B.POINTS_INTERIOR), plan.points(B.POINTS_BOUNDARY))
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    du = torch.zeros(s.n_interface, dtype=torch.float64, device="cuda")
+    dc = torch.zeros(s.nsub * s.neurons, dtype=torch.float64, device="cuda")
+    plan.solve(t(W), t(b), t(f), t(g), None, du, dc)
+    info = plan.solve_info()
+    assert info.status == B.NOT_SPD
+    assert info.bad_subdomain == 2
+
+
+def test_nonfinite_source_is_reported(gpu):
+    import torch
+    from paper_2406_15959_amd import binding as B
+    P = wl.Problem(2, 2, 40, 8, 8, 6, 6, R=2.0)
+    plan = B.Plan(to_c_problem(P))
+    s = plan.sizes
+    W, b = wl.hidden_params(P, 4)
+    f, g, _ = wl.sample_data(P, plan.points(B.POINTS_INTERIOR), plan.points(B.POINTS_BOUNDARY))
+    f[10] = np.nan
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    du = torch.zeros(s.n_interface, dtype=torch.float64, device="cuda")
+    dc = torch.zeros(s.nsub * s.neurons, dtype=torch.float64, device="cuda")
+    plan.solve(t(W), t(b), t(f), t(g), None, du, dc)
+    assert plan.solve_info().status == B.NONFINITE
+
+
+def test_repeated_solves_are_bitwise_reproducible(gpu):
+    P = wl.Problem(3, 3, 60, 10, 10, 8, 6, R=2.0)
+    from paper_2406_15959_amd import binding as B
+    plan = B.Plan(to_c_problem(P))
+    a = gpu_solve(P, 5, plan=plan)
+    b = gpu_solve(P, 5, plan=plan)
+    assert np.array_equal(a["u_gamma"], b["u_gamma"])
+    assert np.array_equal(a["c"], b["c"])

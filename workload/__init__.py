@@ -152,3 +152,17 @@ def eval_grid(problem: Problem, per_sub: int = 16):
             xs.append(X.ravel())
             ys.append(Y.ravel())
     return np.concatenate(xs), np.concatenate(ys)
+
+
+def sample_data(problem: Problem, interior_xy, boundary_xy):
+    """Problem data at given points: f at interior points, g at boundary
+    points, and (a, da/dx, da/dy) stacked as (3, npts) for the variable
+    coefficient operator (None for Poisson)."""
+    interior_xy = np.asarray(interior_xy, dtype=np.float64).reshape(-1, 2)
+    boundary_xy = np.asarray(boundary_xy, dtype=np.float64).reshape(-1, 2)
+    f = source_f(problem, interior_xy[:, 0], interior_xy[:, 1])
+    g = boundary_g(problem, boundary_xy[:, 0], boundary_xy[:, 1])
+    coef = None
+    if problem.op == OP_VARCOEF:
+        coef = np.stack(coefficient(problem, interior_xy[:, 0], interior_xy[:, 1]))
+    return f, g, coef
