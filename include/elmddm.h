@@ -38,7 +38,8 @@
  *
  * Errors: functions return an elmddm_status.  Argument errors are detected
  * on the host before anything is enqueued.  Numerical failures found on the
- * device (a local Gram block or the Schur matrix not positive definite,
+ * device (a local Gram block or the Schur matrix not positive definite: a
+ * Cholesky pivot at or below 64 n u times its original diagonal entry,
  * non-finite values) are recorded in the plan and returned by
  * elmddm_solve_info after synchronisation.  elmddm_last_error() gives a
  * human-readable message for the last failing call on the calling thread.

@@ -60,10 +60,14 @@ void assemble(hipStream_t st, int N, int ldx, int n, const RowTable& rows, const
 void scale_diag(hipStream_t st, double* A, int lda, long long sA, int n, double factor, int batch);
 
 // Factor the jb x jb diagonal block at (j, j) in place (lower), write its inverse to
-// Dinv (ld 64, stride sD) and, if Linv != nullptr, into Linv at (j, j).
+// Dinv (ld 64, stride sD) and, if Linv != nullptr, into Linv at (j, j).  A pivot
+// that is not above tau * dsave[j + k] (the matrix's original diagonal entry;
+// 0 if dsave is null) or not finite marks the matrix as not positive definite.
 void potrf_diag(hipStream_t st, double* A, int lda, long long sA, int j, int jb, double* Dinv,
                 long long sD, double* Linv, int ldl, long long sL, DevInfo* info, int pass,
-                int batch);
+                int batch, const double* dsave, long long sS, double tau);
+void save_diag(hipStream_t st, const double* A, int lda, long long sA, int n, double* d,
+               long long sS, int batch);
 
 void copy_row(hipStream_t st, const double* src, int lds_, long long sS, double* dst, int ldd,
               long long sD, int count, int batch);
@@ -97,9 +101,11 @@ constexpr int NB = 64;  // block size of the blocked Cholesky
 // (Mrows = n or n + 1; an extra last row r becomes r L^{-T}).  Writes the
 // inverses of the 64 x 64 diagonal blocks to Dinv (stride sD per matrix) and,
 // if Linv != nullptr, the inverse factor L^{-1} (strictly upper part untouched).
+// Breakdown: a pivot at or below 64 n u times its original diagonal entry
+// (saved into dsave, stride sS per matrix) is reported through info.
 void blocked_potrf(hipStream_t st, double* A, int lda, long long sA, int Mrows, int n, double* Dinv,
                    long long sD, double* Linv, int ldl, long long sL, double* Tbuf, DevInfo* info,
-                   int pass, int batch);
+                   int pass, int batch, double* dsave, long long sS);
 
 void init_info(hipStream_t st, DevInfo* info);
 void check_finite(hipStream_t st, const double* v, long long count, DevInfo* info);

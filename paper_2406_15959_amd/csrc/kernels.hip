@@ -100,7 +100,7 @@ void assemble(hipStream_t st, int N, int ldx, int n, const RowTable& rows, const
 // Workgroup tile 64x64, K staged 16 at a time through LDS, four waves in a
 // 2x2 arrangement, each wave a 32x32 block of 2x2 V_MFMA_F64_16X16X4 tiles.
 // MFMA operand layout (16x16x4, f64): lane l holds A[l%16][l/16] and
-// B[l/16][l%16]; the accumulator's element r of lane l is D[4*(l/16)+r][l%16].
+// B[l/16][l%16]; the accumulator's element r of lane l is D[4*r + l/16][l%16].
 // The next K stage is fetched into registers while the current one computes.
 // ---------------------------------------------------------------------------
 #define GB_M 64
@@ -229,7 +229,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(
         for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = m0 + wm * 32 + bi * 16 + lq * 4 + r;
+                const int row = m0 + wm * 32 + bi * 16 + r * 4 + lq;
                 const int col = n0 + wn * 32 + bj * 16 + lr;
                 if (row < M && col < N) {
                     const long long ci = (long long)col * ldc + row;
@@ -294,7 +294,9 @@ void scale_diag(hipStream_t st, double* A, int lda, long long sA, int n, double 
 __global__ __launch_bounds__(256) void potrf_diag_kernel(double* A, int lda, long long sA, int j,
                                                          int jb, double* Dinv, long long sD,
                                                          double* Linv, int ldl, long long sL,
-                                                         DevInfo* info, int pass)
+                                                         DevInfo* info, int pass,
+                                                         const double* dsave, long long sS,
+                                                         double tau)
 {
     __shared__ double T[64][65];
     __shared__ double Xi[64][65];
@@ -313,7 +315,8 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* A, int lda, lon
     for (int k = 0; k < jb; ++k) {
         if (tid == 0) {
             double d = T[k][k];
-            if (!(d > 0.0) || !isfinite(d)) {
+            const double floor_ = dsave ? tau * dsave[z * sS + j + k] : 0.0;
+            if (!(d > floor_) || !isfinite(d)) {
                 failed = 1;
                 d = 1.0;
             }
@@ -365,10 +368,25 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* A, int lda, lon
 
 void potrf_diag(hipStream_t st, double* A, int lda, long long sA, int j, int jb, double* Dinv,
                 long long sD, double* Linv, int ldl, long long sL, DevInfo* info, int pass,
-                int batch)
+                int batch, const double* dsave, long long sS, double tau)
 {
     hipLaunchKernelGGL(potrf_diag_kernel, dim3(batch), dim3(256), 0, st, A, lda, sA, j, jb, Dinv,
-                       sD, Linv, ldl, sL, info, pass);
+                       sD, Linv, ldl, sL, info, pass, dsave, sS, tau);
+}
+
+__global__ void save_diag_kernel(const double* A, int lda, long long sA, int n, double* d,
+                                 long long sS)
+{
+    const long long z = blockIdx.y;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[z * sS + i] = A[z * sA + (long long)i * lda + i];
+}
+
+void save_diag(hipStream_t st, const double* A, int lda, long long sA, int n, double* d,
+               long long sS, int batch)
+{
+    dim3 grid((n + 255) / 256, batch);
+    hipLaunchKernelGGL(save_diag_kernel, grid, dim3(256), 0, st, A, lda, sA, n, d, sS);
 }
 
 __global__ void copy_row_kernel(const double* src, int lsrc, long long sS, double* dst, int ldd,

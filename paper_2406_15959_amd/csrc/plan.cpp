@@ -54,7 +54,7 @@ struct elmddm_plan {
     uint64_t bytes = 0;
     double *X0 = nullptr, *X1 = nullptr, *G = nullptr, *Linv[3] = {nullptr, nullptr, nullptr};
     double *Dinv = nullptr, *Tbuf = nullptr, *P = nullptr, *Mbuf = nullptr, *abuf = nullptr;
-    double *Sx = nullptr, *Skeep = nullptr, *DinvS = nullptr, *yvec = nullptr;
+    double *Sx = nullptr, *Skeep = nullptr, *DinvS = nullptr, *yvec = nullptr, *dsave = nullptr;
     double *d_rx = nullptr, *d_ry = nullptr, *d_rnx = nullptr, *d_rny = nullptr;
     double *d_cx = nullptr, *d_cy = nullptr;
     int32_t *d_kind = nullptr, *d_src = nullptr, *d_cmap = nullptr, *d_gidx = nullptr;
@@ -437,6 +437,7 @@ elmddm_status build(elmddm_plan* P)
     TRY(P->dalloc(&P->Sx, (size_t)P->lds * std::max(P->nG, 1)));
     TRY(P->dalloc(&P->DinvS, (size_t)std::max(P->nblkS, 1) * NB * NB));
     TRY(P->dalloc(&P->yvec, (size_t)std::max(P->nG, 1)));
+    TRY(P->dalloc(&P->dsave, std::max((size_t)N * n, (size_t)std::max(P->nG, 1))));
     TRY(P->dalloc(&P->d_info, 1));
     // The strictly upper parts of the inverse factors are never written by the
     // solve and must read as zero.
@@ -617,7 +618,7 @@ elmddm_status elmddm_solve(elmddm_plan* P, const double* W, const double* b, con
         if (P->timing) (void)hipEventRecord(P->pev[3 * (pass - 1) + 1], st);
         if (pass == 1) scale_diag(st, P->G, ldg, P->sG, n, 1.0 + shift, N);
         blocked_potrf(st, P->G, ldg, P->sG, ncol, n, P->Dinv, P->sD, P->Linv[pass - 1], ldg, P->sL,
-                      P->Tbuf, P->d_info, pass, N);
+                      P->Tbuf, P->d_info, pass, N, P->dsave, n);
         if (P->timing) (void)hipEventRecord(P->pev[3 * (pass - 1) + 2], st);
         const int r0 = pass == 3 ? P->mI : 0;
         gemm_f64(st, false, true, 2, false, ldx - r0, n, n, 1.0, src + r0, ldx, P->sX,
@@ -651,7 +652,7 @@ elmddm_status elmddm_solve(elmddm_plan* P, const double* W, const double* b, con
         // Interface solve: Cholesky of [S; rhs^T] gives L and y = L^{-1} rhs,
         // then L^T u = y block by block.
         blocked_potrf(st, P->Sx, P->lds, 0, P->nG + 1, P->nG, P->DinvS, 0, nullptr, 0, 0, nullptr,
-                      P->d_info, 4, 1);
+                      P->d_info, 4, 1, P->dsave, 0);
         copy_row(st, P->Sx + P->nG, P->lds, 0, P->yvec, 1, 0, P->nG, 1);
         P->mark(6, st);
         for (int jb0 = (P->nblkS - 1) * NB; jb0 >= 0; jb0 -= NB) {

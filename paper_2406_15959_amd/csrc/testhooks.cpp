@@ -6,7 +6,26 @@
 
 using namespace elmddm;
 
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// One V_MFMA_F64_16X16X4 with per-lane operands a[lane], b[lane]; writes the
+// raw accumulator: out[lane * 4 + r].
+__global__ void mfma_probe_kernel(const double* a, const double* b, double* out)
+{
+    const int l = threadIdx.x;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[l], b[l], acc, 0, 0, 0);
+    for (int r = 0; r < 4; ++r) out[l * 4 + r] = acc[r];
+}
+
 extern "C" {
+
+// a, b: 64 doubles each (device); out: 256 doubles (device).  One wave.
+int elmddm_test_mfma_layout(const double* a, const double* b, double* out, void* stream)
+{
+    hipLaunchKernelGGL(mfma_probe_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, a, b, out);
+    return hipGetLastError() == hipSuccess ? 0 : 7;
+}
 
 int elmddm_test_gemm(int ta, int tb, int kmode, int lower, int M, int N, int K, double alpha,
                      const double* A, int lda, long long sA, const double* B, int ldb, long long sB,
@@ -23,7 +42,7 @@ int elmddm_test_potrf(double* A, int lda, long long sA, int Mrows, int n, double
                       int batch, void* stream)
 {
     blocked_potrf((hipStream_t)stream, A, lda, sA, Mrows, n, Dinv, sD, Linv, ldl, sL, Tbuf,
-                  reinterpret_cast<DevInfo*>(info), 1, batch);
+                  reinterpret_cast<DevInfo*>(info), 1, batch, nullptr, 0);
     return hipGetLastError() == hipSuccess ? 0 : 7;
 }
 

@@ -20,6 +20,7 @@ def hooks(gpu):
     vp, i32, i64, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_longlong, ctypes.c_double
     L.elmddm_test_gemm.argtypes = [i32, i32, i32, i32, i32, i32, i32, d, vp, i32, i64, vp, i32, i64,
                                    d, vp, i32, i64, i32, vp]
+    L.elmddm_test_mfma_layout.argtypes = [vp, vp, vp, vp]
     L.elmddm_test_potrf.argtypes = [vp, i32, i64, i32, i32, vp, i64, vp, i32, i64, vp, vp, i32, vp]
     return L
 
@@ -36,6 +37,27 @@ def _p(t):
 def _stream():
     import torch
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def test_mfma_f64_lane_layout(hooks):
+    """The GEMM kernel assumes: lane l holds A[l%16][l/16], B[l/16][l%16], and
+    accumulator element r of lane l is D[4r + l/16][l%16]."""
+    import torch
+    rng = np.random.default_rng(0)
+    A = rng.integers(-4, 5, (16, 4)).astype(np.float64)
+    B = rng.integers(-4, 5, (4, 16)).astype(np.float64)
+    lanes = np.arange(64)
+    a = A[lanes % 16, lanes // 16]
+    b = B[lanes // 16, lanes % 16]
+    out = torch.zeros(256, dtype=torch.float64, device="cuda:0")
+    da, db = _dev(a), _dev(b)          # keep the device buffers alive across the launch
+    st = hooks.elmddm_test_mfma_layout(_p(da), _p(db), _p(out), _stream())
+    assert st == 0
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().reshape(64, 4)
+    D = A @ B
+    expect = np.array([[D[4 * r + l // 16, l % 16] for r in range(4)] for l in range(64)])
+    assert np.array_equal(got, expect), got
 
 
 def ref_gemm(ta, tb, kmode, lower, M, N, K, alpha, A, B, beta, C):
