@@ -65,7 +65,8 @@ void scale_diag(hipStream_t st, double* A, int lda, long long sA, int n, double 
 // 0 if dsave is null) or not finite marks the matrix as not positive definite.
 void potrf_diag(hipStream_t st, double* A, int lda, long long sA, int j, int jb, double* Dinv,
                 long long sD, double* Linv, int ldl, long long sL, DevInfo* info, int pass,
-                int batch, const double* dsave, long long sS, double tau);
+                int batch, const double* dsave, long long sS, double tau, double* rhs);
+void rhs_update(hipStream_t st, const double* L, int ld, int j, int jb, int r0, int r1, double* r);
 void save_diag(hipStream_t st, const double* A, int lda, long long sA, int n, double* d,
                long long sS, int batch);
 
@@ -76,20 +77,25 @@ void schur_mblocks(hipStream_t st, int nblk, const int32_t* desc, const double* 
                    long long sP, int cbase, int mg, double* Mbuf);
 void schur_avec(hipStream_t st, int nE, const int32_t* desc, const double* P, int ldp, long long sP,
                 int cbase, int acol, int mg, double* abuf);
+// S blocks and rhs are written at the permuted edge positions perm[E].
 void schur_sblocks(hipStream_t st, int nE, int mg, const int32_t* tptr, const int32_t* tdesc,
                    const int32_t* mptr, const int32_t* mdesc, const double* P, int ldp,
-                   long long sP, const double* Mbuf, double* S, int lds_);
+                   long long sP, const double* Mbuf, double* S, int lds_, const int32_t* perm);
 void schur_rhs(hipStream_t st, int nE, int mg, const int32_t* qdesc, const int32_t* gptr,
                const int32_t* gdesc, const double* P, int ldp, long long sP, int qcol,
-               const double* Mbuf, const double* abuf, double* rhs, int inc);
+               const double* Mbuf, const double* abuf, double* rhs, int inc, const int32_t* perm);
+void unpermute(hipStream_t st, int nE, int mg, const int32_t* perm, const double* up, double* u);
+void unpermute_matrix(hipStream_t st, int nE, int mg, const int32_t* perm, const double* Sp, int lds,
+                      double* S);
 
-void trsv_lower_t_step(hipStream_t st, const double* L, int ld, int j0, int jb, const double* Dinv,
-                       double* y, double* u);
+// One block step of L^T u = y: u_J = Dinv_J^T y_J, y_K -= L_{J,K}^T u_J for K in [kbeg, j0).
+void trsv_lower_t_step(hipStream_t st, const double* L, int ld, int j0, int jb, int kbeg,
+                       const double* Dinv, double* y, double* u);
 
 void local_backsolve(hipStream_t st, int N, int n, int kpad, const double* X, int ldx, long long sX,
                      int mI, int hrow, const int32_t* gidx, const double* u,
                      const double* Linv1, const double* Linv2, const double* Linv3, int ldg,
-                     long long sG, double* c);
+                     long long sG, double* c, double* tmp1, double* tmp2);
 
 void eval_points(hipStream_t st, int npts, const double* xy, int nx, int ny, double x0, double x1,
                  double y0, double y1, int n, const double* W, const double* b, const double* c,
@@ -106,6 +112,14 @@ constexpr int NB = 64;  // block size of the blocked Cholesky
 void blocked_potrf(hipStream_t st, double* A, int lda, long long sA, int Mrows, int n, double* Dinv,
                    long long sD, double* Linv, int ldl, long long sL, double* Tbuf, DevInfo* info,
                    int pass, int batch, double* dsave, long long sS);
+
+// Cholesky of one n x n SPD matrix whose nonzeros lie inside a column
+// envelope: rend[p] = one past the last row that may be nonzero in the
+// columns of 64-wide panel p (nondecreasing).  Fill-in stays inside the
+// envelope, so panel and trailing updates are restricted to it.  rhs (n) is
+// overwritten by L^{-1} rhs (forward substitution fused with the panels).
+void envelope_potrf(hipStream_t st, double* A, int lda, int n, const int* rend, double* Dinv,
+                    DevInfo* info, int pass, double* dsave, double* rhs);
 
 void init_info(hipStream_t st, DevInfo* info);
 void check_finite(hipStream_t st, const double* v, long long count, DevInfo* info);

@@ -288,74 +288,192 @@ void scale_diag(hipStream_t st, double* A, int lda, long long sA, int n, double 
     hipLaunchKernelGGL(scale_diag_kernel, grid, dim3(256), 0, st, A, lda, sA, n, factor);
 }
 
-// Unblocked Cholesky of a jb x jb (jb <= 64) diagonal block held in LDS, then
-// the inverse of its factor by row-wise forward substitution.  A pivot that is
-// not positive and finite marks the matrix as not positive definite.
+// Value of v in lane k, broadcast to the whole wave (k uniform).
+__device__ __forceinline__ double lane_bcast(double v, int k)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), k);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), k);
+    return __hiloint2double(hi, lo);
+}
+
+// 16x16 tile product on the matrix cores: acc += A * B, where the wave's lane
+// l supplies A[l%16][4s + l/16] and B[4s + l/16][l%16] for s = 0..3 through
+// the accessors; acc element r of lane l is C[4r + l/16][l%16].
+template <class FA, class FB>
+__device__ __forceinline__ v4d mfma16(v4d acc, FA fa, FB fb)
+{
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(fa(s4), fb(s4), acc, 0, 0, 0);
+    return acc;
+}
+
+// Cholesky of the jb x jb (jb <= 64) diagonal block at (j, j) and the inverse
+// of its factor, by one workgroup of four waves with the block in LDS (rows
+// and columns beyond jb are identity).  The block is processed as four
+// 16-wide column panels: wave 0 factors the 16 x 16 diagonal tile in
+// registers (lane i holds row i; pivots and columns move between lanes by
+// lane reads) together with its inverse; the panel below is multiplied by that
+// inverse and the trailing tiles are updated with 16x16x4 FP64 MFMA tiles
+// spread over the waves.  The full inverse X = L^{-1} is then assembled from
+// the diagonal-tile inverses by diagonals:
+//     X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj   (16 x 16 tiles, i > j).
 __global__ __launch_bounds__(256) void potrf_diag_kernel(double* A, int lda, long long sA, int j,
                                                          int jb, double* Dinv, long long sD,
                                                          double* Linv, int ldl, long long sL,
                                                          DevInfo* info, int pass,
                                                          const double* dsave, long long sS,
-                                                         double tau)
+                                                         double tau, double* rhs)
 {
     __shared__ double T[64][65];
-    __shared__ double Xi[64][65];
-    __shared__ int failed;
+    __shared__ double Xs[64][65];
+    __shared__ double tmp[4][16][17];
+    __shared__ double fl[64];
+    __shared__ int bad_any;
     const int z = blockIdx.x;
     A += z * sA;
     Dinv += z * sD;
     const int tid = threadIdx.x;
-    if (tid == 0) failed = 0;
+    const int lane = tid & 63;
+    const int w = tid >> 6;
+    const int lr = lane & 15, lq = lane >> 4;
+    if (tid == 0) bad_any = 0;
     for (int idx = tid; idx < 64 * 64; idx += 256) {
-        const int i = idx & 63, c = idx >> 6;
-        T[i][c] = (i < jb && c < jb && i >= c) ? A[(long long)(j + c) * lda + (j + i)] : 0.0;
-        Xi[i][c] = 0.0;
+        const int c = idx >> 6, r = idx & 63;   // column-major walk: coalesced loads
+        double v = (r == c) ? 1.0 : 0.0;
+        if (r < jb && c < jb && r >= c) v = A[(long long)(j + c) * lda + (j + r)];
+        T[r][c] = v;
+        Xs[r][c] = 0.0;
+    }
+    if (tid < 64) fl[tid] = (dsave && tid < jb) ? tau * dsave[z * sS + j + tid] : 0.0;
+    __syncthreads();
+
+    for (int sb = 0; sb < 4; ++sb) {
+        const int s0 = 16 * sb;
+        if (w == 0) {
+            // factor the 16 x 16 diagonal tile: lane i (< 16) holds row i
+            const int i = lane;
+            double r[16], x[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) r[c] = (i < 16 && c <= i) ? T[s0 + i][s0 + c] : 0.0;
+            const double myfl = i < 16 ? fl[s0 + i] : 0.0;
+            int bad = 0;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                double d = lane_bcast(r[k], k);
+                const double f = lane_bcast(myfl, k);
+                if (!(d > f) || !isfinite(d)) {
+                    bad = 1;
+                    d = 1.0;
+                }
+                const double p = sqrt(d);
+                const double rp = 1.0 / p;
+                r[k] = (i == k) ? p : ((i > k) ? r[k] * rp : r[k]);
+#pragma unroll
+                for (int c = k + 1; c < 16; ++c) {
+                    const double lck = lane_bcast(r[k], c);
+                    if (i > k) r[c] -= r[k] * lck;
+                }
+            }
+            // inverse of the tile: lane i holds row i of X
+#pragma unroll
+            for (int c = 0; c < 16; ++c) x[c] = (c == i) ? 1.0 : 0.0;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const double rkk = 1.0 / lane_bcast(r[k], k);
+#pragma unroll
+                for (int c = 0; c <= k; ++c) {
+                    if (i == k) x[c] *= rkk;
+                    const double xk = lane_bcast(x[c], k);
+                    if (i > k) x[c] -= r[k] * xk;
+                }
+            }
+            if (i < 16) {
+#pragma unroll
+                for (int c = 0; c < 16; ++c) {
+                    if (c <= i) {
+                        T[s0 + i][s0 + c] = r[c];
+                        Xs[s0 + i][s0 + c] = x[c];
+                    }
+                }
+            }
+            if (bad && lane == 0) bad_any = 1;
+        }
+        __syncthreads();
+        if (sb == 3) break;
+        // panel: rows below, T[rt][s0 tile] = T[rt][s0 tile] * X_ss^T
+        const int nrt = 3 - sb;
+        if (w < nrt) {
+            const int rt = s0 + 16 * (w + 1);
+            v4d acc = {0.0, 0.0, 0.0, 0.0};
+            acc = mfma16(acc, [&](int s4) { return T[rt + lr][s0 + 4 * s4 + lq]; },
+                         [&](int s4) { return Xs[s0 + lr][s0 + 4 * s4 + lq]; });
+#pragma unroll
+            for (int r = 0; r < 4; ++r) T[rt + 4 * r + lq][s0 + lr] = acc[r];
+        }
+        __syncthreads();
+        // trailing: T[ti][tj] -= P_ti P_tj^T for tiles below the panel, ti >= tj
+        int pairs[6][2];
+        int np = 0;
+        for (int a = 1; a <= nrt; ++a)
+            for (int b = 1; b <= a; ++b) {
+                pairs[np][0] = s0 + 16 * a;
+                pairs[np][1] = s0 + 16 * b;
+                ++np;
+            }
+        for (int pi = w; pi < np; pi += 4) {
+            const int ti = pairs[pi][0], tj = pairs[pi][1];
+            v4d acc = {0.0, 0.0, 0.0, 0.0};
+            acc = mfma16(acc, [&](int s4) { return T[ti + lr][s0 + 4 * s4 + lq]; },
+                         [&](int s4) { return T[tj + lr][s0 + 4 * s4 + lq]; });
+#pragma unroll
+            for (int r = 0; r < 4; ++r) T[ti + 4 * r + lq][tj + lr] -= acc[r];
+        }
+        __syncthreads();
+    }
+
+    // full inverse by diagonals of 16 x 16 tiles
+    for (int d = 1; d < 4; ++d) {
+        const int bi = d + w, bj = w;   // waves 0 .. 3-d handle tile (bi, bj)
+        const bool act = (w < 4 - d);
+        if (act) {
+            v4d acc = {0.0, 0.0, 0.0, 0.0};
+            for (int kb = bj; kb < bi; ++kb)
+                acc = mfma16(acc, [&](int s4) { return T[16 * bi + lr][16 * kb + 4 * s4 + lq]; },
+                             [&](int s4) { return Xs[16 * kb + 4 * s4 + lq][16 * bj + lr]; });
+#pragma unroll
+            for (int r = 0; r < 4; ++r) tmp[w][4 * r + lq][lr] = acc[r];
+        }
+        __syncthreads();
+        if (act) {
+            v4d acc = {0.0, 0.0, 0.0, 0.0};
+            acc = mfma16(acc, [&](int s4) { return Xs[16 * bi + lr][16 * bi + 4 * s4 + lq]; },
+                         [&](int s4) { return tmp[w][4 * s4 + lq][lr]; });
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Xs[16 * bi + 4 * r + lq][16 * bj + lr] = -acc[r];
+        }
+        __syncthreads();
+    }
+
+    if (rhs) {
+        // forward substitution for this block: y_J = L_JJ^{-1} r_J
+        if (tid < 64) fl[tid] = tid < jb ? rhs[j + tid] : 0.0;   // fl is free by now
+        __syncthreads();
+        if (tid < jb) {
+            double acc = 0.0;
+            for (int c = 0; c <= tid; ++c) acc += Xs[tid][c] * fl[c];
+            rhs[j + tid] = acc;
+        }
+    }
+    for (int idx = tid; idx < 64 * 64; idx += 256) {
+        const int c = idx >> 6, r = idx & 63;
+        const bool in = (r < jb) && (c < jb);
+        const double xv = (in && c <= r) ? Xs[r][c] : 0.0;
+        Dinv[c * 64 + r] = xv;
+        if (in && c <= r) A[(long long)(j + c) * lda + (j + r)] = T[r][c];
+        if (Linv && in) Linv[z * sL + (long long)(j + c) * ldl + (j + r)] = xv;
     }
     __syncthreads();
-    for (int k = 0; k < jb; ++k) {
-        if (tid == 0) {
-            double d = T[k][k];
-            const double floor_ = dsave ? tau * dsave[z * sS + j + k] : 0.0;
-            if (!(d > floor_) || !isfinite(d)) {
-                failed = 1;
-                d = 1.0;
-            }
-            T[k][k] = sqrt(d);
-        }
-        __syncthreads();
-        const double dk = T[k][k];
-        for (int i = k + 1 + tid; i < jb; i += 256) T[i][k] /= dk;
-        __syncthreads();
-        const int w = jb - k - 1;
-        for (int idx = tid; idx < w * w; idx += 256) {
-            const int i = k + 1 + idx / w, c = k + 1 + idx % w;
-            if (c <= i) T[i][c] -= T[i][k] * T[c][k];
-        }
-        __syncthreads();
-    }
-    // Xi = T^{-1}: row i from rows < i.
-    for (int i = 0; i < jb; ++i) {
-        if (tid < jb) {
-            const int c = tid;
-            if (c < i) {
-                double acc = 0.0;
-                for (int k = c; k < i; ++k) acc += T[i][k] * Xi[k][c];
-                Xi[i][c] = -acc / T[i][i];
-            } else if (c == i) {
-                Xi[i][i] = 1.0 / T[i][i];
-            }
-        }
-        __syncthreads();
-    }
-    for (int idx = tid; idx < 64 * 64; idx += 256) {
-        const int i = idx & 63, c = idx >> 6;
-        Dinv[c * 64 + i] = Xi[i][c];
-        if (i < jb && c < jb) {
-            if (i >= c) A[(long long)(j + c) * lda + (j + i)] = T[i][c];
-            if (Linv) Linv[z * sL + (long long)(j + c) * ldl + (j + i)] = Xi[i][c];
-        }
-    }
-    if (tid == 0 && failed && info) {
+    if (tid == 0 && bad_any && info) {
         if (pass <= 3) {
             atomicMin(&info->bad_subdomain, z);
             atomicMax(&info->bad_pass, pass);
@@ -368,10 +486,30 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* A, int lda, lon
 
 void potrf_diag(hipStream_t st, double* A, int lda, long long sA, int j, int jb, double* Dinv,
                 long long sD, double* Linv, int ldl, long long sL, DevInfo* info, int pass,
-                int batch, const double* dsave, long long sS, double tau)
+                int batch, const double* dsave, long long sS, double tau, double* rhs)
 {
     hipLaunchKernelGGL(potrf_diag_kernel, dim3(batch), dim3(256), 0, st, A, lda, sA, j, jb, Dinv,
-                       sD, Linv, ldl, sL, info, pass, dsave, sS, tau);
+                       sD, Linv, ldl, sL, info, pass, dsave, sS, tau, rhs);
+}
+
+// r_I -= L_{I,J} y_J for the rows I = [r0, r1) below a factored panel J = [j, j + jb).
+__global__ void rhs_update_kernel(const double* L, int ld, int j, int jb, int r0, int r1, double* r)
+{
+    __shared__ double yj[64];
+    if (threadIdx.x < 64) yj[threadIdx.x] = threadIdx.x < jb ? r[j + threadIdx.x] : 0.0;
+    __syncthreads();
+    const int row = r0 + blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= r1) return;
+    double acc = 0.0;
+    for (int c = 0; c < jb; ++c) acc += L[(long long)(j + c) * ld + row] * yj[c];
+    r[row] -= acc;
+}
+
+void rhs_update(hipStream_t st, const double* L, int ld, int j, int jb, int r0, int r1, double* r)
+{
+    if (r1 <= r0) return;
+    hipLaunchKernelGGL(rhs_update_kernel, dim3((r1 - r0 + 255) / 256), dim3(256), 0, st, L, ld, j, jb,
+                       r0, r1, r);
 }
 
 __global__ void save_diag_kernel(const double* A, int lda, long long sA, int n, double* d,
@@ -471,7 +609,8 @@ __global__ __launch_bounds__(256) void schur_sblocks_kernel(int nE, int mg, cons
                                                             const int32_t* mptr,
                                                             const int32_t* mdesc, const double* P,
                                                             int ldp, long long sP,
-                                                            const double* Mbuf, double* S, int lds)
+                                                            const double* Mbuf, double* S, int lds,
+                                                            const int32_t* perm)
 {
     __shared__ double M1[64 * 64];
     __shared__ double M2[64 * 64];
@@ -521,25 +660,25 @@ __global__ __launch_bounds__(256) void schur_sblocks_kernel(int nE, int mg, cons
         const int idx = tid + 256 * t;
         if (idx < mm) {
             const int r = idx % mg, c = idx / mg;
-            S[(long long)(E2 * mg + c) * lds + (E1 * mg + r)] = acc[t];
+            S[(long long)(perm[E2] * mg + c) * lds + (perm[E1] * mg + r)] = acc[t];
         }
     }
 }
 
 void schur_sblocks(hipStream_t st, int nE, int mg, const int32_t* tptr, const int32_t* tdesc,
                    const int32_t* mptr, const int32_t* mdesc, const double* P, int ldp,
-                   long long sP, const double* Mbuf, double* S, int lds)
+                   long long sP, const double* Mbuf, double* S, int lds, const int32_t* perm)
 {
     if (nE <= 0) return;
     hipLaunchKernelGGL(schur_sblocks_kernel, dim3(nE, nE), dim3(256), 0, st, nE, mg, tptr, tdesc,
-                       mptr, mdesc, P, ldp, sP, Mbuf, S, lds);
+                       mptr, mdesc, P, ldp, sP, Mbuf, S, lds, perm);
 }
 
 // rhs_E = sum_s q_s(E) - sum_g M_{g,E}^T a_g.
 __global__ void schur_rhs_kernel(int mg, const int32_t* qdesc, const int32_t* gptr,
                                  const int32_t* gdesc, const double* P, int ldp, long long sP,
                                  int qcol, const double* Mbuf, const double* abuf, double* rhs,
-                                 int inc)
+                                 int inc, const int32_t* perm)
 {
     const int E = blockIdx.x;
     const int mm = mg * mg;
@@ -558,17 +697,17 @@ __global__ void schur_rhs_kernel(int mg, const int32_t* qdesc, const int32_t* gp
             for (int p = 0; p < mg; ++p) acc += Mb[r * mg + p] * ag[p];
             v -= acc;
         }
-        rhs[(long long)(E * mg + r) * inc] = v;
+        rhs[(long long)(perm[E] * mg + r) * inc] = v;
     }
 }
 
 void schur_rhs(hipStream_t st, int nE, int mg, const int32_t* qdesc, const int32_t* gptr,
                const int32_t* gdesc, const double* P, int ldp, long long sP, int qcol,
-               const double* Mbuf, const double* abuf, double* rhs, int inc)
+               const double* Mbuf, const double* abuf, double* rhs, int inc, const int32_t* perm)
 {
     if (nE <= 0) return;
     hipLaunchKernelGGL(schur_rhs_kernel, dim3(nE), dim3(64), 0, st, mg, qdesc, gptr, gdesc, P, ldp,
-                       sP, qcol, Mbuf, abuf, rhs, inc);
+                       sP, qcol, Mbuf, abuf, rhs, inc, perm);
 }
 
 // ---------------------------------------------------------------------------
@@ -578,85 +717,138 @@ void schur_rhs(hipStream_t st, int nE, int mg, const int32_t* qdesc, const int32
 // inter-workgroup ordering.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void trsv_lt_step_kernel(const double* L, int ld, int j0, int jb,
-                                                           const double* Dinv, double* y,
+                                                           int kbeg, const double* Dinv, double* y,
                                                            double* u)
 {
     __shared__ double yj[64], uj[64];
     const int tid = threadIdx.x;
-    if (tid < jb) yj[tid] = y[j0 + tid];
+    if (tid < 64) yj[tid] = tid < jb ? y[j0 + tid] : 0.0;
     __syncthreads();
-    if (tid < jb) {
+    if (tid < 64) {
         double s = 0.0;
         for (int i = tid; i < jb; ++i) s += Dinv[tid * 64 + i] * yj[i];
         uj[tid] = s;
     }
     __syncthreads();
     if (blockIdx.x == 0 && tid < jb) u[j0 + tid] = uj[tid];
-    const int kcol = blockIdx.x * 256 + tid;
-    if (kcol < j0) {
-        const double* col = L + (long long)kcol * ld + j0;
-        double s = 0.0;
-        for (int i = 0; i < jb; ++i) s += col[i] * uj[i];
-        y[kcol] -= s;
+    // one wave per column K < j0: lanes run over the 64 rows of block row J
+    const int lane = tid & 63;
+    const int wave = blockIdx.x * 4 + (tid >> 6);
+    const int nwave = gridDim.x * 4;
+    const double ul = lane < jb ? uj[lane] : 0.0;
+    for (int kcol = kbeg + wave; kcol < j0; kcol += nwave) {
+        double v = lane < jb ? L[(long long)kcol * ld + j0 + lane] * ul : 0.0;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) y[kcol] -= v;
     }
 }
 
-void trsv_lower_t_step(hipStream_t st, const double* L, int ld, int j0, int jb, const double* Dinv,
-                       double* y, double* u)
+void trsv_lower_t_step(hipStream_t st, const double* L, int ld, int j0, int jb, int kbeg,
+                       const double* Dinv, double* y, double* u)
 {
-    const int nb = j0 > 0 ? (j0 + 255) / 256 : 1;
-    hipLaunchKernelGGL(trsv_lt_step_kernel, dim3(nb), dim3(256), 0, st, L, ld, j0, jb, Dinv, y, u);
+    int nb = (j0 - kbeg + 15) / 16;   // about 4 columns per wave
+    nb = nb < 1 ? 1 : (nb > 1024 ? 1024 : nb);
+    hipLaunchKernelGGL(trsv_lt_step_kernel, dim3(nb), dim3(256), 0, st, L, ld, j0, jb, kbeg, Dinv, y,
+                       u);
 }
 
 // ---------------------------------------------------------------------------
 // Local back-solve (Algorithm 1, last loop): c = R^{-1} (h + Q_Gamma^T u_s)
 // with R^{-1} = Linv1^T Linv2^T Linv3^T from the three CholeskyQR passes.
+// One wave per output entry, lanes along the contiguous column: coalesced.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void local_backsolve_kernel(int n, int kpad, const double* X,
-                                                              int ldx, long long sX, int mI,
-                                                              int hrow, const int32_t* gidx,
-                                                              const double* u, const double* L1,
-                                                              const double* L2, const double* L3,
-                                                              int ldg, long long sG, double* c)
+__device__ __forceinline__ double wave_sum(double v)
 {
-    extern __shared__ double sh[];
-    double* v = sh;
-    double* w = sh + n;
-    const int s = blockIdx.x;
-    const double* Xs = X + s * sX;
-    for (int col = threadIdx.x; col < n; col += blockDim.x) {
-        const double* xc = Xs + (long long)col * ldx;
-        double acc = xc[hrow];
-        for (int i = 0; i < kpad; ++i) {
-            const int gi = gidx[s * kpad + i];
-            if (gi >= 0) acc += xc[mI + i] * u[gi];
-        }
-        v[col] = acc;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// v[s][col] = h_s[col] + sum_i Q_Gamma[i][col] u[gidx_s[i]]
+__global__ __launch_bounds__(256) void bs_rhs_kernel(int n, int kpad, const double* X, int ldx,
+                                                     long long sX, int mI, int hrow,
+                                                     const int32_t* gidx, const double* u,
+                                                     double* v)
+{
+    const int s = blockIdx.y;
+    const int lane = threadIdx.x & 63;
+    const int col = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (col >= n) return;
+    const double* xc = X + s * sX + (long long)col * ldx;
+    double acc = 0.0;
+    for (int i = lane; i < kpad; i += 64) {
+        const int gi = gidx[s * kpad + i];
+        if (gi >= 0) acc += xc[mI + i] * u[gi];
     }
-    __syncthreads();
-    const double* Ls[3] = {L3 + s * sG, L2 + s * sG, L1 + s * sG};
-    for (int p = 0; p < 3; ++p) {
-        const double* Li = Ls[p];
-        double* in = (p & 1) ? w : v;
-        double* out = (p & 1) ? v : w;
-        for (int i = threadIdx.x; i < n; i += blockDim.x) {
-            const double* colp = Li + (long long)i * ldg;
-            double acc = 0.0;
-            for (int k = i; k < n; ++k) acc += colp[k] * in[k];
-            out[i] = acc;
-        }
-        __syncthreads();
-    }
-    // after three passes the result is in w
-    for (int i = threadIdx.x; i < n; i += blockDim.x) c[(long long)s * n + i] = w[i];
+    acc = wave_sum(acc);
+    if (lane == 0) v[(long long)s * n + col] = acc + xc[hrow];
+}
+
+// out[s][i] = sum_{k >= i} Li[s][k + i*ldg] in[s][k]   (Linv^T times a vector)
+__global__ __launch_bounds__(256) void trmv_t_kernel(int n, const double* Li, int ldg, long long sG,
+                                                     const double* in, double* out)
+{
+    const int s = blockIdx.y;
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= n) return;
+    const double* colp = Li + s * sG + (long long)i * ldg;
+    const double* vin = in + (long long)s * n;
+    double acc = 0.0;
+    for (int k = i + lane; k < n; k += 64) acc += colp[k] * vin[k];
+    acc = wave_sum(acc);
+    if (lane == 0) out[(long long)s * n + i] = acc;
 }
 
 void local_backsolve(hipStream_t st, int N, int n, int kpad, const double* X, int ldx, long long sX,
                      int mI, int hrow, const int32_t* gidx, const double* u, const double* Linv1,
-                     const double* Linv2, const double* Linv3, int ldg, long long sG, double* c)
+                     const double* Linv2, const double* Linv3, int ldg, long long sG, double* c,
+                     double* tmp1, double* tmp2)
 {
-    hipLaunchKernelGGL(local_backsolve_kernel, dim3(N), dim3(256), 2 * n * sizeof(double), st, n,
-                       kpad, X, ldx, sX, mI, hrow, gidx, u, Linv1, Linv2, Linv3, ldg, sG, c);
+    dim3 grid((n + 3) / 4, N);
+    hipLaunchKernelGGL(bs_rhs_kernel, grid, dim3(256), 0, st, n, kpad, X, ldx, sX, mI, hrow, gidx, u,
+                       tmp1);
+    hipLaunchKernelGGL(trmv_t_kernel, grid, dim3(256), 0, st, n, Linv3, ldg, sG, tmp1, tmp2);
+    hipLaunchKernelGGL(trmv_t_kernel, grid, dim3(256), 0, st, n, Linv2, ldg, sG, tmp2, tmp1);
+    hipLaunchKernelGGL(trmv_t_kernel, grid, dim3(256), 0, st, n, Linv1, ldg, sG, tmp1, c);
+}
+
+// u[E*mg + r] = up[perm[E]*mg + r]
+__global__ void unpermute_kernel(int nE, int mg, const int32_t* perm, const double* up, double* u)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nE * mg) return;
+    const int E = idx / mg, r = idx % mg;
+    u[idx] = up[(long long)perm[E] * mg + r];
+}
+
+void unpermute(hipStream_t st, int nE, int mg, const int32_t* perm, const double* up, double* u)
+{
+    if (nE <= 0) return;
+    hipLaunchKernelGGL(unpermute_kernel, dim3((nE * mg + 255) / 256), dim3(256), 0, st, nE, mg, perm,
+                       up, u);
+}
+
+// Dense S in the original interface order from the permuted copy (ld lds).
+__global__ void unpermute_matrix_kernel(int nE, int mg, const int32_t* perm, const double* Sp, int lds,
+                                        double* S)
+{
+    const long long n = (long long)nE * mg;
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * n) return;
+    const int row = (int)(idx % n), col = (int)(idx / n);
+    const int pr = perm[row / mg] * mg + row % mg, pc = perm[col / mg] * mg + col % mg;
+    S[idx] = Sp[(long long)pc * lds + pr];
+}
+
+void unpermute_matrix(hipStream_t st, int nE, int mg, const int32_t* perm, const double* Sp, int lds,
+                      double* S)
+{
+    const long long n = (long long)nE * mg;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(unpermute_matrix_kernel, dim3((unsigned)((n * n + 255) / 256)), dim3(256), 0, st,
+                       nE, mg, perm, Sp, lds, S);
 }
 
 // ---------------------------------------------------------------------------

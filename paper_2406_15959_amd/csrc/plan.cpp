@@ -55,6 +55,10 @@ struct elmddm_plan {
     double *X0 = nullptr, *X1 = nullptr, *G = nullptr, *Linv[3] = {nullptr, nullptr, nullptr};
     double *Dinv = nullptr, *Tbuf = nullptr, *P = nullptr, *Mbuf = nullptr, *abuf = nullptr;
     double *Sx = nullptr, *Skeep = nullptr, *DinvS = nullptr, *yvec = nullptr, *dsave = nullptr;
+    double *uperm = nullptr, *bs1 = nullptr, *bs2 = nullptr;
+    int32_t* d_perm = nullptr;
+    std::vector<int> rend;   // per 64-panel of S: one past the last row of the envelope
+    std::vector<int> kbeg;   // per 64-block row of S: first column reaching it
     double *d_rx = nullptr, *d_ry = nullptr, *d_rnx = nullptr, *d_rny = nullptr;
     double *d_cx = nullptr, *d_cy = nullptr;
     int32_t *d_kind = nullptr, *d_src = nullptr, *d_cmap = nullptr, *d_gidx = nullptr;
@@ -399,6 +403,52 @@ elmddm_status build(elmddm_plan* P)
         gdesc.insert(gdesc.end(), gl[e].begin(), gl[e].end());
     }
 
+    // Edge order for the interface system: by edge midpoint (y, then x).  With
+    // this order S is confined to a narrow envelope around its diagonal.
+    std::vector<int32_t> perm(P->nE, 0);
+    {
+        std::vector<std::pair<std::pair<double, double>, int>> key(P->nE);
+        for (int e = 0; e < P->nE; ++e) {
+            double mx, my;
+            if (e < nV) {
+                const int i = e % (nx - 1) + 1, j = e / (nx - 1);
+                mx = p.x0 + i * hx;
+                my = p.y0 + (j + 0.5) * hy;
+            } else {
+                const int e2 = e - nV, i = e2 % nx, j = e2 / nx + 1;
+                mx = p.x0 + (i + 0.5) * hx;
+                my = p.y0 + j * hy;
+            }
+            key[e] = {{my, mx}, e};
+        }
+        std::sort(key.begin(), key.end());
+        for (int r = 0; r < P->nE; ++r) perm[key[r].second] = r;
+        std::vector<int> lastb(P->nE, 0);
+        for (int e2 = 0; e2 < P->nE; ++e2) lastb[perm[e2]] = perm[e2];
+        for (int e1 = 0; e1 < P->nE; ++e1)
+            for (int e2 = 0; e2 < P->nE; ++e2) {
+                const size_t blk = (size_t)e1 + (size_t)e2 * P->nE;
+                if (tl[blk].empty() && ml[blk].empty()) continue;
+                const int p1 = perm[e1], p2 = perm[e2];
+                if (p1 > p2) lastb[p2] = std::max(lastb[p2], p1);
+            }
+        std::vector<int> env(P->nG, 0);
+        int run = 0;
+        for (int c = 0; c < P->nG; ++c) {
+            run = std::max(run, (lastb[c / mg] + 1) * mg - 1);
+            env[c] = run;
+        }
+        P->rend.assign(P->nblkS, 0);
+        P->kbeg.assign(P->nblkS, 0);
+        for (int pb = 0; pb < P->nblkS; ++pb) {
+            const int j0 = pb * NB;
+            P->rend[pb] = std::min(P->nG, env[std::min(j0 + NB - 1, P->nG - 1)] + 1);
+            int c = 0;
+            while (c < j0 && env[c] < j0) ++c;
+            P->kbeg[pb] = c;
+        }
+    }
+
     // ---- device allocations ----
     elmddm_status st;
 #define TRY(x)                       \
@@ -425,6 +475,7 @@ elmddm_status build(elmddm_plan* P)
     TRY(P->upload(&P->d_mlist, mlist));
     TRY(P->upload(&P->d_gptr, gptr));
     TRY(P->upload(&P->d_gdesc, gdesc));
+    TRY(P->upload(&P->d_perm, perm));
     TRY(P->dalloc(&P->X0, (size_t)N * P->sX));
     TRY(P->dalloc(&P->X1, (size_t)N * P->sX));
     TRY(P->dalloc(&P->G, (size_t)N * P->sG));
@@ -438,6 +489,9 @@ elmddm_status build(elmddm_plan* P)
     TRY(P->dalloc(&P->DinvS, (size_t)std::max(P->nblkS, 1) * NB * NB));
     TRY(P->dalloc(&P->yvec, (size_t)std::max(P->nG, 1)));
     TRY(P->dalloc(&P->dsave, std::max((size_t)N * n, (size_t)std::max(P->nG, 1))));
+    TRY(P->dalloc(&P->uperm, (size_t)std::max(P->nG, 1)));
+    TRY(P->dalloc(&P->bs1, (size_t)N * n));
+    TRY(P->dalloc(&P->bs2, (size_t)N * n));
     TRY(P->dalloc(&P->d_info, 1));
     // The strictly upper parts of the inverse factors are never written by the
     // solve and must read as zero.
@@ -572,11 +626,10 @@ elmddm_status elmddm_get_schur(elmddm_plan* P, double* S, double* rhs, void* str
     if (!P->schur_valid) return fail(ELMDDM_INVALID_ARG, "no Schur system kept (call elmddm_plan_keep_schur before solving)");
     hipStream_t st = (hipStream_t)stream;
     if (P->nG == 0) return ELMDDM_OK;
-    // S: the first nG rows of each column; rhs: row nG.
-    if (hipMemcpy2DAsync(S, (size_t)P->nG * sizeof(double), P->Skeep, (size_t)P->lds * sizeof(double),
-                         (size_t)P->nG * sizeof(double), P->nG, hipMemcpyDeviceToDevice, st) != hipSuccess)
-        return check_launch("get_schur");
-    copy_row(st, P->Skeep + P->nG, P->lds, 0, rhs, 1, 0, P->nG, 1);
+    // The kept copy is in the permuted edge order: S in the first nG rows, rhs in row nG.
+    unpermute_matrix(st, P->nE, P->mg, P->d_perm, P->Skeep, P->lds, S);
+    copy_row(st, P->Skeep + P->nG, P->lds, 0, P->uperm, 1, 0, P->nG, 1);
+    unpermute(st, P->nE, P->mg, P->d_perm, P->uperm, rhs);
     return check_launch("get_schur");
 }
 
@@ -640,26 +693,29 @@ elmddm_status elmddm_solve(elmddm_plan* P, const double* W, const double* b, con
         schur_mblocks(st, P->n_mblocks, P->d_mdesc, P->P, P->ldp, P->sP, cbase, P->mg, P->Mbuf);
         schur_avec(st, P->nE, P->d_adesc, P->P, P->ldp, P->sP, cbase, P->kpad, P->mg, P->abuf);
         schur_sblocks(st, P->nE, P->mg, P->d_tptr, P->d_tdesc, P->d_mptr, P->d_mlist, P->P, P->ldp,
-                      P->sP, P->Mbuf, P->Sx, P->lds);
+                      P->sP, P->Mbuf, P->Sx, P->lds, P->d_perm);
         schur_rhs(st, P->nE, P->mg, P->d_qdesc, P->d_gptr, P->d_gdesc, P->P, P->ldp, P->sP, P->kpad,
-                  P->Mbuf, P->abuf, P->Sx + P->nG, P->lds);
+                  P->Mbuf, P->abuf, P->yvec, 1, P->d_perm);
         P->mark(5, st);
         if (P->keep_schur && P->Skeep) {
             (void)hipMemcpyAsync(P->Skeep, P->Sx, (size_t)P->lds * P->nG * sizeof(double),
                                  hipMemcpyDeviceToDevice, st);
+            copy_row(st, P->yvec, 1, 0, P->Skeep + P->nG, P->lds, 0, P->nG, 1);
             P->schur_valid = true;
         }
-        // Interface solve: Cholesky of [S; rhs^T] gives L and y = L^{-1} rhs,
-        // then L^T u = y block by block.
-        blocked_potrf(st, P->Sx, P->lds, 0, P->nG + 1, P->nG, P->DinvS, 0, nullptr, 0, 0, nullptr,
-                      P->d_info, 4, 1, P->dsave, 0);
-        copy_row(st, P->Sx + P->nG, P->lds, 0, P->yvec, 1, 0, P->nG, 1);
+        // Interface solve in the permuted order: envelope Cholesky with the
+        // forward substitution fused (yvec <- L^{-1} rhs), then L^T u = y
+        // block by block, then back to the interface numbering.
+        envelope_potrf(st, P->Sx, P->lds, P->nG, P->rend.data(), P->DinvS, P->d_info, 4, P->dsave,
+                       P->yvec);
         P->mark(6, st);
-        for (int jb0 = (P->nblkS - 1) * NB; jb0 >= 0; jb0 -= NB) {
+        for (int pb = P->nblkS - 1; pb >= 0; --pb) {
+            const int jb0 = pb * NB;
             const int jb = std::min(NB, P->nG - jb0);
-            trsv_lower_t_step(st, P->Sx, P->lds, jb0, jb, P->DinvS + (long long)(jb0 / NB) * NB * NB,
-                              P->yvec, u_gamma);
+            trsv_lower_t_step(st, P->Sx, P->lds, jb0, jb, P->kbeg[pb],
+                              P->DinvS + (long long)pb * NB * NB, P->yvec, P->uperm);
         }
+        unpermute(st, P->nE, P->mg, P->d_perm, P->uperm, u_gamma);
         est = check_launch("interface solve");
         if (est != ELMDDM_OK) return est;
     } else {
@@ -668,7 +724,7 @@ elmddm_status elmddm_solve(elmddm_plan* P, const double* W, const double* b, con
     }
     P->mark(7, st);
     local_backsolve(st, N, n, P->kpad, dst, ldx, P->sX, P->mI, P->hrow, P->d_gidx, u_gamma,
-                    P->Linv[0], P->Linv[1], P->Linv[2], ldg, P->sL, c);
+                    P->Linv[0], P->Linv[1], P->Linv[2], ldg, P->sL, c, P->bs1, P->bs2);
     const long long nc = (long long)N * n;
     P->mark(8, st);
     check_finite(st, c, nc, P->d_info);
