@@ -89,6 +89,7 @@ typedef struct elmddm_problem {
 /* Sizes derived from a problem (filled by elmddm_plan_sizes). */
 typedef struct elmddm_sizes {
     int32_t nsub;            /* number of subdomains N                          */
+    int32_t batch;           /* problem instances per solve                     */
     int32_t neurons;         /* n_N                                             */
     int32_t n_interior;      /* interior points per subdomain (q_x * q_y)       */
     int32_t n_interface;     /* interface unknowns nG                           */
@@ -103,7 +104,7 @@ typedef struct elmddm_info {
     int32_t status;          /* elmddm_status of the last solve                 */
     int32_t bad_subdomain;   /* first subdomain whose local factorisation failed, else -1 */
     int32_t bad_pass;        /* CholeskyQR pass (1..3) of that failure, else 0  */
-    int32_t reserved;
+    int32_t bad_instance;    /* problem instance of that failure, else -1       */
 } elmddm_info;
 
 typedef struct elmddm_plan elmddm_plan;
@@ -114,6 +115,17 @@ typedef struct elmddm_plan elmddm_plan;
  * as many interior points as neurons per subdomain); otherwise INVALID_ARG.
  * On failure *plan is set to NULL. */
 elmddm_status elmddm_plan_create(const elmddm_problem* problem, elmddm_plan** plan);
+
+/* As elmddm_plan_create, for `batch` independent instances of the same
+ * problem geometry solved together: every per-instance argument of
+ * elmddm_solve gains a leading [batch] dimension (W [batch][nsub][neurons][2],
+ * b, f, g, coef [3][batch][nsub][q_x*q_y], u_gamma [batch][n_interface],
+ * c [batch][nsub][neurons]).  All stages run over the whole batch in the same
+ * launches.  elmddm_plan_create is elmddm_plan_create_batch with batch = 1.
+ * elmddm_assemble writes all batch * nsub subdomains; elmddm_get_schur
+ * returns instance 0. */
+elmddm_status elmddm_plan_create_batch(const elmddm_problem* problem, int32_t batch,
+                                       elmddm_plan** plan);
 
 /* Release the plan and its device memory.  NULL is accepted. */
 elmddm_status elmddm_plan_destroy(elmddm_plan* plan);

@@ -30,7 +30,7 @@ POINTS_BOUNDARY = 1
 POINTS_INTERFACE = 2
 
 EXPORTED = [
-    "elmddm_plan_create", "elmddm_plan_destroy", "elmddm_plan_sizes", "elmddm_points",
+    "elmddm_plan_create", "elmddm_plan_create_batch", "elmddm_plan_destroy", "elmddm_plan_sizes", "elmddm_points",
     "elmddm_solve", "elmddm_solve_info", "elmddm_eval", "elmddm_assemble",
     "elmddm_plan_keep_schur", "elmddm_get_schur", "elmddm_set_timing", "elmddm_stage_times",
     "elmddm_status_string", "elmddm_last_error",
@@ -49,7 +49,7 @@ class Problem(ctypes.Structure):
 
 
 class Sizes(ctypes.Structure):
-    _fields_ = [("nsub", ctypes.c_int32), ("neurons", ctypes.c_int32), ("n_interior", ctypes.c_int32),
+    _fields_ = [("nsub", ctypes.c_int32), ("batch", ctypes.c_int32), ("neurons", ctypes.c_int32), ("n_interior", ctypes.c_int32),
                 ("n_interface", ctypes.c_int32), ("n_boundary", ctypes.c_int64),
                 ("max_rows", ctypes.c_int32), ("max_ifc", ctypes.c_int32),
                 ("device_bytes", ctypes.c_uint64)]
@@ -57,7 +57,7 @@ class Sizes(ctypes.Structure):
 
 class Info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("bad_subdomain", ctypes.c_int32),
-                ("bad_pass", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("bad_pass", ctypes.c_int32), ("bad_instance", ctypes.c_int32)]
 
 
 class ElmddmError(RuntimeError):
@@ -78,6 +78,7 @@ def lib():
         L = ctypes.CDLL(_LIB_PATH)
         vp, dp, i32, i64 = ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
         L.elmddm_plan_create.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(vp)]
+        L.elmddm_plan_create_batch.argtypes = [ctypes.POINTER(Problem), i32, ctypes.POINTER(vp)]
         L.elmddm_plan_destroy.argtypes = [vp]
         L.elmddm_plan_sizes.argtypes = [vp, ctypes.POINTER(Sizes)]
         L.elmddm_points.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), i64]
@@ -127,9 +128,9 @@ def make_problem(x0=0.0, x1=1.0, y0=0.0, y1=1.0, nsub_x=1, nsub_y=1, neurons=1, 
 class Plan:
     """Owns an elmddm_plan (host layout + device workspace)."""
 
-    def __init__(self, problem: Problem):
+    def __init__(self, problem: Problem, batch: int = 1):
         self._h = ctypes.c_void_p()
-        _check(lib().elmddm_plan_create(ctypes.byref(problem), ctypes.byref(self._h)))
+        _check(lib().elmddm_plan_create_batch(ctypes.byref(problem), batch, ctypes.byref(self._h)))
         s = Sizes()
         _check(lib().elmddm_plan_sizes(self._h, ctypes.byref(s)))
         self.sizes = s

@@ -49,13 +49,18 @@ struct DevInfo {
 void gemm_f64(hipStream_t st, bool ta, bool tb, int kmode, bool lower, int M, int N, int K,
               double alpha, const double* A, int lda, long long sA, const double* B, int ldb,
               long long sB, double beta, double* C, int ldc, long long sC, int batch);
+// Kernel variant for large (which = 0, >= 2^30 multiply-adds) or small (1) products:
+// bit 1 = K depth 32 instead of 16, bit 0 = XCD-aware tile order.
+void set_gemm_variant(int which, int v);
 
 // Writes X (plan layout, ldx rows x (n+1) columns per subdomain) or, if Kout != nullptr,
 // the compact K^s [n][ldK], A^s [n][ldD] and F^s [ldF] per subdomain.
-void assemble(hipStream_t st, int N, int ldx, int n, const RowTable& rows, const SubGeom& geom,
-              int op, const double* W, const double* b, const double* f, const double* g,
-              const double* coef, int q2, double* X, double* Fout, int ldF, double* Kout, int ldK,
-              double* Dout, int ldD);
+// N counts the subdomains of the whole batch; subdomain s has geometry s % ngeo and
+// belongs to instance s / ngeo (whose boundary data start at instance * nbnd).
+void assemble(hipStream_t st, int N, int ngeo, long long nbnd, int ldx, int n, const RowTable& rows,
+              const SubGeom& geom, int op, const double* W, const double* b, const double* f,
+              const double* g, const double* coef, int q2, double* X, double* Fout, int ldF,
+              double* Kout, int ldK, double* Dout, int ldD);
 
 void scale_diag(hipStream_t st, double* A, int lda, long long sA, int n, double factor, int batch);
 
@@ -65,35 +70,45 @@ void scale_diag(hipStream_t st, double* A, int lda, long long sA, int n, double 
 // 0 if dsave is null) or not finite marks the matrix as not positive definite.
 void potrf_diag(hipStream_t st, double* A, int lda, long long sA, int j, int jb, double* Dinv,
                 long long sD, double* Linv, int ldl, long long sL, DevInfo* info, int pass,
-                int batch, const double* dsave, long long sS, double tau, double* rhs);
-void rhs_update(hipStream_t st, const double* L, int ld, int j, int jb, int r0, int r1, double* r);
+                int batch, const double* dsave, long long sS, double tau, double* rhs,
+                long long sR);
+// Panel, trailing update and forward-substitution update of one envelope
+// Cholesky step (see envelope_potrf); L tiles below the diagonal go to Lo.
+void envelope_step(hipStream_t st, double* A, int lda, long long sA, double* Lo, int ldo,
+                   long long sLo, int j, int jb, const double* Dinv, long long sD, int r1,
+                   double* rhs, long long sR, int batch);
+// Backward substitution over a block row of br <= 256 rows (four 64-row sub-blocks).
+void trsv_lower_t_block(hipStream_t st, const double* L, int ld, long long sL, int j0, int br,
+                        int kbeg, const double* Dinv, long long sD, double* y, double* u,
+                        long long sY, int batch);
 void save_diag(hipStream_t st, const double* A, int lda, long long sA, int n, double* d,
                long long sS, int batch);
 
 void copy_row(hipStream_t st, const double* src, int lds_, long long sS, double* dst, int ldd,
               long long sD, int count, int batch);
 
+// The Schur-assembly kernels run over ninst problem instances; P holds ngeo
+// subdomains per instance.
 void schur_mblocks(hipStream_t st, int nblk, const int32_t* desc, const double* P, int ldp,
-                   long long sP, int cbase, int mg, double* Mbuf);
+                   long long sP, int cbase, int mg, double* Mbuf, int ngeo, int ninst);
 void schur_avec(hipStream_t st, int nE, const int32_t* desc, const double* P, int ldp, long long sP,
-                int cbase, int acol, int mg, double* abuf);
+                int cbase, int acol, int mg, double* abuf, int ngeo, int ninst);
 // S blocks and rhs are written at the permuted edge positions perm[E].
 void schur_sblocks(hipStream_t st, int nE, int mg, const int32_t* tptr, const int32_t* tdesc,
                    const int32_t* mptr, const int32_t* mdesc, const double* P, int ldp,
-                   long long sP, const double* Mbuf, double* S, int lds_, const int32_t* perm);
+                   long long sP, const double* Mbuf, double* S, int lds_, const int32_t* perm,
+                   int ngeo, long long sM, long long sS, int ninst);
 void schur_rhs(hipStream_t st, int nE, int mg, const int32_t* qdesc, const int32_t* gptr,
                const int32_t* gdesc, const double* P, int ldp, long long sP, int qcol,
-               const double* Mbuf, const double* abuf, double* rhs, int inc, const int32_t* perm);
-void unpermute(hipStream_t st, int nE, int mg, const int32_t* perm, const double* up, double* u);
+               const double* Mbuf, const double* abuf, double* rhs, int inc, const int32_t* perm,
+               int ngeo, long long sM, long long sA, long long sR, int ninst);
+void unpermute(hipStream_t st, int nE, int mg, const int32_t* perm, const double* up, double* u,
+               int ninst);
 void unpermute_matrix(hipStream_t st, int nE, int mg, const int32_t* perm, const double* Sp, int lds,
                       double* S);
 
-// One block step of L^T u = y: u_J = Dinv_J^T y_J, y_K -= L_{J,K}^T u_J for K in [kbeg, j0).
-void trsv_lower_t_step(hipStream_t st, const double* L, int ld, int j0, int jb, int kbeg,
-                       const double* Dinv, double* y, double* u);
-
-void local_backsolve(hipStream_t st, int N, int n, int kpad, const double* X, int ldx, long long sX,
-                     int mI, int hrow, const int32_t* gidx, const double* u,
+void local_backsolve(hipStream_t st, int N, int ngeo, long long nG, int n, int kpad, const double* X,
+                     int ldx, long long sX, int mI, int hrow, const int32_t* gidx, const double* u,
                      const double* Linv1, const double* Linv2, const double* Linv3, int ldg,
                      long long sG, double* c, double* tmp1, double* tmp2);
 
@@ -118,8 +133,11 @@ void blocked_potrf(hipStream_t st, double* A, int lda, long long sA, int Mrows, 
 // columns of 64-wide panel p (nondecreasing).  Fill-in stays inside the
 // envelope, so panel and trailing updates are restricted to it.  rhs (n) is
 // overwritten by L^{-1} rhs (forward substitution fused with the panels).
-void envelope_potrf(hipStream_t st, double* A, int lda, int n, const int* rend, double* Dinv,
-                    DevInfo* info, int pass, double* dsave, double* rhs);
+// The strictly lower 64 x 64 tiles of L are written to Lo (ld ldo); the
+// diagonal tiles stay in A and their inverses in Dinv.
+void envelope_potrf(hipStream_t st, double* A, int lda, long long sA, double* Lo, int ldo,
+                    long long sLo, int n, const int* rend, double* Dinv, long long sD, DevInfo* info,
+                    int pass, double* dsave, double* rhs, long long sR, int batch);
 
 void init_info(hipStream_t st, DevInfo* info);
 void check_finite(hipStream_t st, const double* v, long long count, DevInfo* info);

@@ -11,6 +11,14 @@ namespace elmddm {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+
 // ---------------------------------------------------------------------------
 // Feature assembly (paper, Section 3, eq. nonoverlap_discrete; Section 4.1):
 // one row per collocation point, one column per neuron plus the rhs column.
@@ -28,17 +36,21 @@ __global__ __launch_bounds__(256) void assemble_kernel(
     const double* __restrict__ bias, const double* __restrict__ f, const double* __restrict__ g,
     const double* __restrict__ coef, long long coef_stride, double* __restrict__ X, long long sX,
     bool compact, double* __restrict__ Fout, int ldF, double* __restrict__ Kout, int ldK,
-    long long sK, double* __restrict__ Dout, int ldD, long long sD)
+    long long sK, double* __restrict__ Dout, int ldD, long long sD, int ngeo, int q2, long long nbnd)
 {
-    const int s = blockIdx.z;
+    const int s = blockIdx.z;            // subdomain of the whole batch
+    const int sg = s % ngeo;             // its geometry
+    const long long inst = s / ngeo;     // its problem instance
     const int r = blockIdx.x * 64 + (threadIdx.x & 63);
     const int cg = threadIdx.x >> 6;
     if (r >= ldx) return;
-    const long long ri = (long long)s * ldx + r;
+    const long long ri = (long long)sg * ldx + r;
     const int kind = rows.kind[ri];
-    const int src = rows.src[ri];
-    const double xh = (rows.x[ri] - geom.cx[s]) * geom.sx;
-    const double yh = (rows.y[ri] - geom.cy[s]) * geom.sy;
+    // data index: interior rows -> s * q2 + i, boundary rows -> instance * nbnd + global index
+    const long long src = kind == ROW_INTERIOR ? rows.src[ri] + inst * ngeo * (long long)q2
+                                               : rows.src[ri] + inst * nbnd;
+    const double xh = (rows.x[ri] - geom.cx[sg]) * geom.sx;
+    const double yh = (rows.y[ri] - geom.cy[sg]) * geom.sy;
     const double nxv = rows.nx[ri], nyv = rows.ny[ri];
     double a = 1.0, ax = 0.0, ay = 0.0;
     if (op == 1 && kind == ROW_INTERIOR) {
@@ -83,38 +95,51 @@ __global__ __launch_bounds__(256) void assemble_kernel(
     }
 }
 
-void assemble(hipStream_t st, int N, int ldx, int n, const RowTable& rows, const SubGeom& geom,
-              int op, const double* W, const double* b, const double* f, const double* g,
-              const double* coef, int q2, double* X, double* Fout, int ldF, double* Kout, int ldK,
-              double* Dout, int ldD)
+void assemble(hipStream_t st, int N, int ngeo, long long nbnd, int ldx, int n, const RowTable& rows,
+              const SubGeom& geom, int op, const double* W, const double* b, const double* f,
+              const double* g, const double* coef, int q2, double* X, double* Fout, int ldF,
+              double* Kout, int ldK, double* Dout, int ldD)
 {
     dim3 grid((ldx + 63) / 64, (n + 1 + 63) / 64, N);
     const bool compact = (Kout != nullptr);
     hipLaunchKernelGGL(assemble_kernel, grid, dim3(256), 0, st, ldx, n, rows, geom, op, W, b, f, g,
                        coef, (long long)N * q2, X, (long long)ldx * (n + 1), compact, Fout, ldF,
-                       Kout, ldK, (long long)ldK * n, Dout, ldD, (long long)ldD * n);
+                       Kout, ldK, (long long)ldK * n, Dout, ldD, (long long)ldD * n, ngeo, q2, nbnd);
 }
 
 // ---------------------------------------------------------------------------
 // Batched FP64 GEMM on the matrix cores: C = alpha op(A) op(B) + beta C.
-// Workgroup tile 64x64, K staged 16 at a time through LDS, four waves in a
+// Workgroup tile 64x64, K staged 32 at a time through LDS, four waves in a
 // 2x2 arrangement, each wave a 32x32 block of 2x2 V_MFMA_F64_16X16X4 tiles.
 // MFMA operand layout (16x16x4, f64): lane l holds A[l%16][l/16] and
 // B[l/16][l%16]; the accumulator's element r of lane l is D[4*r + l/16][l%16].
-// The next K stage is fetched into registers while the current one computes.
+// Global loads move 8 consecutive doubles per thread (16-byte vector loads
+// when aligned and in bounds); the next K stage is fetched into registers
+// while the current one computes.  Workgroups are renumbered so that each
+// XCD (the hardware deals workgroups to the 8 XCDs in turn) receives a
+// contiguous run of tiles, i.e. whole matrices of the batch, and their
+// operands stay in that XCD's L2.
 // ---------------------------------------------------------------------------
 #define GB_M 64
 #define GB_N 64
-#define GB_K 16
 
-template <bool TA, bool TB, int KMODE, bool LOWER>
+__device__ __forceinline__ bool aligned16(const double* p)
+{
+    return (reinterpret_cast<uintptr_t>(p) & 15u) == 0;
+}
+
+template <bool TA, bool TB, int KMODE, bool LOWER, int GB_K, bool XCD>
 __global__ __launch_bounds__(256) void gemm_f64_kernel(
     int M, int N, int K, double alpha, const double* A, int lda, long long sA, const double* B,
     int ldb, long long sB, double beta, double* C, int ldc, long long sC)
 {
-    const int tm = blockIdx.x, tn = blockIdx.y;
+    const unsigned gx = gridDim.x, gy = gridDim.y;
+    const unsigned total = gx * gy * gridDim.z;
+    const unsigned p = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const unsigned q = (!XCD || (total & 7u)) ? p : (p & 7u) * (total >> 3) + (p >> 3);
+    const int tm = q % gx, tn = (q / gx) % gy;
+    const long long z = q / (gx * gy);
     if (LOWER && tm < tn) return;
-    const long long z = blockIdx.z;
     A += z * sA;
     B += z * sB;
     C += z * sC;
@@ -134,64 +159,64 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
 
-    double ra[4], rb[4];
-    // Thread -> tile element mapping for global loads.
-    // "contiguous-in-row" pattern: k = tid/16, 4 consecutive m (or n) from (tid%16)*4.
-    // "contiguous-in-k" pattern:   m (or n) = tid/4, 4 consecutive k from (tid%4)*4.
+    // Per thread and stage: V = GB_K / 4 consecutive doubles of A and of B.
+    // "along-row": k = tid / (64 / V), V consecutive m (or n) from (tid % (64/V)) * V.
+    // "along-k":   m (or n) = tid / 4, V consecutive k from (tid % 4) * V.
+    constexpr int V = GB_K / 4;
+    constexpr int RS = 64 / V;   // threads per k row in the along-row pattern
+    double ra[V], rb[V];
+    auto loadv = [&](double (&r)[V], const double* p, bool all, auto ok) {
+        if (all && aligned16(p)) {
+            const double2* q2 = reinterpret_cast<const double2*>(p);
+#pragma unroll
+            for (int e = 0; e < V / 2; ++e) {
+                const double2 v = q2[e];
+                r[2 * e] = v.x;
+                r[2 * e + 1] = v.y;
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < V; ++e) r[e] = ok(e) ? p[e] : 0.0;
+        }
+    };
     auto load = [&](int k0) {
         if (!TA) {
-            const int k = tid >> 4, m = (tid & 15) * 4;
-            const int kk = k0 + k;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int mm = m0 + m + e;
-                ra[e] = (kk < kend && mm < M) ? A[(long long)kk * lda + mm] : 0.0;
-            }
+            const int kk = k0 + tid / RS, mm = m0 + (tid % RS) * V;
+            const double* pa = A + (long long)kk * lda + mm;
+            loadv(ra, pa, kk < kend && mm + V - 1 < M, [&](int e) { return kk < kend && mm + e < M; });
         } else {
-            const int m = tid >> 2, k = (tid & 3) * 4;
-            const int mm = m0 + m;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int kk = k0 + k + e;
-                ra[e] = (kk < kend && mm < M) ? A[(long long)mm * lda + kk] : 0.0;
-            }
+            const int mm = m0 + (tid >> 2), kk = k0 + (tid & 3) * V;
+            const double* pa = A + (long long)mm * lda + kk;
+            loadv(ra, pa, mm < M && kk + V - 1 < kend, [&](int e) { return mm < M && kk + e < kend; });
         }
         if (!TB) {
-            const int nn_ = tid >> 2, k = (tid & 3) * 4;
-            const int nn = n0 + nn_;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int kk = k0 + k + e;
-                rb[e] = (kk < kend && nn < N) ? B[(long long)nn * ldb + kk] : 0.0;
-            }
+            const int nn = n0 + (tid >> 2), kk = k0 + (tid & 3) * V;
+            const double* pb = B + (long long)nn * ldb + kk;
+            loadv(rb, pb, nn < N && kk + V - 1 < kend, [&](int e) { return nn < N && kk + e < kend; });
         } else {
-            const int k = tid >> 4, nn_ = (tid & 15) * 4;
-            const int kk = k0 + k;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int nn = n0 + nn_ + e;
-                rb[e] = (kk < kend && nn < N) ? B[(long long)kk * ldb + nn] : 0.0;
-            }
+            const int kk = k0 + tid / RS, nn = n0 + (tid % RS) * V;
+            const double* pb = B + (long long)kk * ldb + nn;
+            loadv(rb, pb, kk < kend && nn + V - 1 < N, [&](int e) { return kk < kend && nn + e < N; });
         }
     };
     auto store = [&]() {
         if (!TA) {
-            const int k = tid >> 4, m = (tid & 15) * 4;
+            const int k = tid / RS, m = (tid % RS) * V;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) As[k][m + e] = ra[e];
+            for (int e = 0; e < V; ++e) As[k][m + e] = ra[e];
         } else {
-            const int m = tid >> 2, k = (tid & 3) * 4;
+            const int m = tid >> 2, k = (tid & 3) * V;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) As[k + e][m] = ra[e];
+            for (int e = 0; e < V; ++e) As[k + e][m] = ra[e];
         }
         if (!TB) {
-            const int nn_ = tid >> 2, k = (tid & 3) * 4;
+            const int nn = tid >> 2, k = (tid & 3) * V;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) Bs[k + e][nn_] = rb[e];
+            for (int e = 0; e < V; ++e) Bs[k + e][nn] = rb[e];
         } else {
-            const int k = tid >> 4, nn_ = (tid & 15) * 4;
+            const int k = tid / RS, nn = (tid % RS) * V;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) Bs[k][nn_ + e] = rb[e];
+            for (int e = 0; e < V; ++e) Bs[k][nn + e] = rb[e];
         }
     };
 
@@ -240,14 +265,36 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(
             }
 }
 
-template <bool TA, bool TB, int KMODE, bool LOWER>
+// Kernel variant (K depth 16 or 32, XCD-aware tile order on/off); index =
+// (bk32 ? 2 : 0) + (xcd ? 1 : 0).  Selected per call class by gemm_variant.
+static int g_gemm_variant[2] = {1, 0};   // [0]: large batched products, [1]: small ones
+
+void set_gemm_variant(int which, int v)
+{
+    if (which >= 0 && which < 2 && v >= 0 && v < 4) g_gemm_variant[which] = v;
+}
+
+template <bool TA, bool TB, int KMODE, bool LOWER, int BK, bool XCD>
 static void gemm_launch(hipStream_t st, int M, int N, int K, double alpha, const double* A, int lda,
                         long long sA, const double* B, int ldb, long long sB, double beta,
                         double* C, int ldc, long long sC, int batch)
 {
     dim3 grid((M + GB_M - 1) / GB_M, (N + GB_N - 1) / GB_N, batch);
-    hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, KMODE, LOWER>), grid, dim3(256), 0, st, M, N, K,
-                       alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+    hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, KMODE, LOWER, BK, XCD>), grid, dim3(256), 0, st, M,
+                       N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+}
+
+template <bool TA, bool TB, int KMODE, bool LOWER>
+static void gemm_dispatch(int variant, hipStream_t st, int M, int N, int K, double alpha,
+                          const double* A, int lda, long long sA, const double* B, int ldb,
+                          long long sB, double beta, double* C, int ldc, long long sC, int batch)
+{
+    switch (variant) {
+        case 0: gemm_launch<TA, TB, KMODE, LOWER, 16, false>(st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch); break;
+        case 1: gemm_launch<TA, TB, KMODE, LOWER, 16, true>(st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch); break;
+        case 2: gemm_launch<TA, TB, KMODE, LOWER, 32, false>(st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch); break;
+        default: gemm_launch<TA, TB, KMODE, LOWER, 32, true>(st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch); break;
+    }
 }
 
 void gemm_f64(hipStream_t st, bool ta, bool tb, int kmode, bool lower, int M, int N, int K,
@@ -255,11 +302,13 @@ void gemm_f64(hipStream_t st, bool ta, bool tb, int kmode, bool lower, int M, in
               long long sB, double beta, double* C, int ldc, long long sC, int batch)
 {
     if (M <= 0 || N <= 0 || batch <= 0) return;
-#define GEMM_CASE(TA_, TB_, KM_, LO_)                                                            \
-    if (ta == TA_ && tb == TB_ && kmode == KM_ && lower == LO_) {                                 \
-        gemm_launch<TA_, TB_, KM_, LO_>(st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, \
-                                        sC, batch);                                              \
-        return;                                                                                  \
+    const long long work = (long long)M * N * (K > 0 ? K : 1) * batch;
+    const int variant = g_gemm_variant[work >= (1LL << 30) ? 0 : 1];
+#define GEMM_CASE(TA_, TB_, KM_, LO_)                                                               \
+    if (ta == TA_ && tb == TB_ && kmode == KM_ && lower == LO_) {                                    \
+        gemm_dispatch<TA_, TB_, KM_, LO_>(variant, st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, \
+                                          C, ldc, sC, batch);                                       \
+        return;                                                                                     \
     }
     GEMM_CASE(false, false, 0, false)
     GEMM_CASE(false, true, 0, false)
@@ -322,7 +371,7 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* A, int lda, lon
                                                          double* Linv, int ldl, long long sL,
                                                          DevInfo* info, int pass,
                                                          const double* dsave, long long sS,
-                                                         double tau, double* rhs)
+                                                         double tau, double* rhs, long long sR)
 {
     __shared__ double T[64][65];
     __shared__ double Xs[64][65];
@@ -350,51 +399,83 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* A, int lda, lon
     for (int sb = 0; sb < 4; ++sb) {
         const int s0 = 16 * sb;
         if (w == 0) {
-            // factor the 16 x 16 diagonal tile: lane i (< 16) holds row i
-            const int i = lane;
-            double r[16], x[16];
+            // Factor the 16 x 16 diagonal tile and invert it with the whole wave:
+            // lane l holds row i = l % 16, columns c = 4t + l / 16 (t = 0..3).
+            // Step k publishes column k (resp. row k of the inverse) in LDS;
+            // LDS operations of one wave complete in program order, so a
+            // scheduling fence between publishing and reading is enough.
+            const int i = lane & 15, q = lane >> 4;
+            double r[4], x[4];
 #pragma unroll
-            for (int c = 0; c < 16; ++c) r[c] = (i < 16 && c <= i) ? T[s0 + i][s0 + c] : 0.0;
-            const double myfl = i < 16 ? fl[s0 + i] : 0.0;
+            for (int t = 0; t < 4; ++t) {
+                const int c = 4 * t + q;
+                r[t] = (c <= i) ? T[s0 + i][s0 + c] : 0.0;
+                x[t] = (c == i) ? 1.0 : 0.0;
+            }
+            double* colb = &tmp[0][0][0];      // 16 entries: column k
+            double* rowb = &tmp[0][1][0];      // 16 entries: row k of the inverse
+            double rpiv[16];                   // 1 / L_kk
             int bad = 0;
 #pragma unroll
             for (int k = 0; k < 16; ++k) {
-                double d = lane_bcast(r[k], k);
-                const double f = lane_bcast(myfl, k);
+                if (q == (k & 3)) colb[i] = r[k >> 2];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                double d = colb[k];
+                const double f = fl[s0 + k];
                 if (!(d > f) || !isfinite(d)) {
                     bad = 1;
                     d = 1.0;
                 }
-                const double p = sqrt(d);
-                const double rp = 1.0 / p;
-                r[k] = (i == k) ? p : ((i > k) ? r[k] * rp : r[k]);
+                // 1/sqrt(d): hardware estimate refined by two Newton steps
+                double rp = __builtin_amdgcn_rsq(d);
+                rp = rp * (1.5 - 0.5 * d * rp * rp);
+                rp = rp * (1.5 - 0.5 * d * rp * rp);
+                const double p = d * rp;
+                rpiv[k] = rp;
+                const double lik = (i > k) ? colb[i] * rp : 0.0;
 #pragma unroll
-                for (int c = k + 1; c < 16; ++c) {
-                    const double lck = lane_bcast(r[k], c);
-                    if (i > k) r[c] -= r[k] * lck;
+                for (int t = 0; t < 4; ++t) {
+                    const int c = 4 * t + q;
+                    if (c == k) r[t] = (i == k) ? p : lik;
+                    else if (c > k && c <= i) r[t] -= lik * (colb[c] * rp);
                 }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
             }
-            // inverse of the tile: lane i holds row i of X
+            // publish L, then X = L^{-1} row by row
 #pragma unroll
-            for (int c = 0; c < 16; ++c) x[c] = (c == i) ? 1.0 : 0.0;
+            for (int t = 0; t < 4; ++t) {
+                const int c = 4 * t + q;
+                if (c <= i) T[s0 + i][s0 + c] = r[t];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
 #pragma unroll
             for (int k = 0; k < 16; ++k) {
-                const double rkk = 1.0 / lane_bcast(r[k], k);
+                const double rkk = rpiv[k];
+                if (i == k) {
 #pragma unroll
-                for (int c = 0; c <= k; ++c) {
-                    if (i == k) x[c] *= rkk;
-                    const double xk = lane_bcast(x[c], k);
-                    if (i > k) x[c] -= r[k] * xk;
-                }
-            }
-            if (i < 16) {
-#pragma unroll
-                for (int c = 0; c < 16; ++c) {
-                    if (c <= i) {
-                        T[s0 + i][s0 + c] = r[c];
-                        Xs[s0 + i][s0 + c] = x[c];
+                    for (int t = 0; t < 4; ++t) {
+                        x[t] *= rkk;
+                        rowb[4 * t + q] = x[t];
                     }
                 }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                const double lik = (i > k) ? T[s0 + i][s0 + k] : 0.0;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int c = 4 * t + q;
+                    if (c <= k) x[t] -= lik * rowb[c];
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int c = 4 * t + q;
+                if (c <= i) Xs[s0 + i][s0 + c] = x[t];
             }
             if (bad && lane == 0) bad_any = 1;
         }
@@ -456,6 +537,7 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* A, int lda, lon
 
     if (rhs) {
         // forward substitution for this block: y_J = L_JJ^{-1} r_J
+        rhs += z * sR;
         if (tid < 64) fl[tid] = tid < jb ? rhs[j + tid] : 0.0;   // fl is free by now
         __syncthreads();
         if (tid < jb) {
@@ -486,30 +568,196 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* A, int lda, lon
 
 void potrf_diag(hipStream_t st, double* A, int lda, long long sA, int j, int jb, double* Dinv,
                 long long sD, double* Linv, int ldl, long long sL, DevInfo* info, int pass,
-                int batch, const double* dsave, long long sS, double tau, double* rhs)
+                int batch, const double* dsave, long long sS, double tau, double* rhs, long long sR)
 {
     hipLaunchKernelGGL(potrf_diag_kernel, dim3(batch), dim3(256), 0, st, A, lda, sA, j, jb, Dinv,
-                       sD, Linv, ldl, sL, info, pass, dsave, sS, tau, rhs);
+                       sD, Linv, ldl, sL, info, pass, dsave, sS, tau, rhs, sR);
 }
 
-// r_I -= L_{I,J} y_J for the rows I = [r0, r1) below a factored panel J = [j, j + jb).
-__global__ void rhs_update_kernel(const double* L, int ld, int j, int jb, int r0, int r1, double* r)
+// One step of the envelope Cholesky after the diagonal block J = [j, j + jb)
+// has been factored (Dinv = L_JJ^{-1}): for the 64-row tiles I >= I' of the
+// band [j + jb, r1), one workgroup per tile pair forms the panel tiles
+// L_I = A_IJ Dinv^T and L_I' (on the matrix cores, from LDS), applies the
+// trailing update A_II' -= L_I L_I'^T in place and, on diagonal pairs, stores
+// L_I into the factor Lo and applies the forward-substitution update
+// y_I -= L_I y_J.  L goes to a separate matrix because other workgroups of the
+// same launch still read the unsolved panel A_IJ.
+__global__ __launch_bounds__(256) void envelope_step_kernel(double* A, int lda, long long sA,
+                                                            double* Lo, int ldo, long long sLo,
+                                                            int j, int jb, const double* Dinv,
+                                                            long long sD, int r1, double* rhs,
+                                                            long long sR)
 {
+    {
+        const long long zb = blockIdx.y;
+        A += zb * sA;
+        Lo += zb * sLo;
+        Dinv += zb * sD;
+        if (rhs) rhs += zb * sR;
+    }
+    __shared__ double Dv[64][65];
+    __shared__ double S1[64][65];
+    __shared__ double S2[64][65];
     __shared__ double yj[64];
-    if (threadIdx.x < 64) yj[threadIdx.x] = threadIdx.x < jb ? r[j + threadIdx.x] : 0.0;
+    const int p = blockIdx.x;
+    int a = (int)((sqrt(8.0 * p + 1.0) - 1.0) * 0.5);
+    while ((a + 1) * (a + 2) / 2 <= p) ++a;
+    while (a * (a + 1) / 2 > p) --a;
+    const int b = p - a * (a + 1) / 2;
+    const int base = j + jb;
+    const int I = base + 64 * a, Ib = base + 64 * b;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int lr = lane & 15, lq = lane >> 4;
+    for (int idx = tid; idx < 64 * 64; idx += 256) {
+        const int c = idx >> 6, r = idx & 63;
+        Dv[r][c] = (r < jb && c < jb) ? Dinv[c * 64 + r] : 0.0;
+        S1[r][c] = (I + r < r1 && c < jb) ? A[(long long)(j + c) * lda + I + r] : 0.0;
+        S2[r][c] = (a != b && Ib + r < r1 && c < jb) ? A[(long long)(j + c) * lda + Ib + r] : 0.0;
+    }
+    if (tid < 64) yj[tid] = (rhs && tid < jb) ? rhs[j + tid] : 0.0;
     __syncthreads();
-    const int row = r0 + blockIdx.x * blockDim.x + threadIdx.x;
-    if (row >= r1) return;
-    double acc = 0.0;
-    for (int c = 0; c < jb; ++c) acc += L[(long long)(j + c) * ld + row] * yj[c];
-    r[row] -= acc;
+    // panel tiles: L = P Dinv^T, each wave a 32 x 32 quarter (2 x 2 MFMA tiles)
+    auto panel = [&](double (*Sx)[65]) {
+        v4d acc[2][2];
+        for (int u = 0; u < 2; ++u)
+            for (int v = 0; v < 2; ++v) acc[u][v] = (v4d){0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < 64; k0 += 4) {
+            const int kk = k0 + lq;
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int v = 0; v < 2; ++v)
+                    acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                        Sx[wm * 32 + u * 16 + lr][kk], Dv[wn * 32 + v * 16 + lr][kk], acc[u][v], 0, 0, 0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int v = 0; v < 2; ++v)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) Sx[wm * 32 + u * 16 + 4 * r + lq][wn * 32 + v * 16 + lr] = acc[u][v][r];
+        __syncthreads();
+    };
+    panel(S1);
+    if (a != b) panel(S2);
+    double (*Lb)[65] = (a != b) ? S2 : S1;
+    // trailing tile C = A[I, Ib] - L_I L_Ib^T
+    v4d acc[2][2];
+    for (int u = 0; u < 2; ++u)
+        for (int v = 0; v < 2; ++v) acc[u][v] = (v4d){0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < 64; k0 += 4) {
+        const int kk = k0 + lq;
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int v = 0; v < 2; ++v)
+                acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                    S1[wm * 32 + u * 16 + lr][kk], Lb[wn * 32 + v * 16 + lr][kk], acc[u][v], 0, 0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = I + wm * 32 + u * 16 + 4 * r + lq;
+                const int col = Ib + wn * 32 + v * 16 + lr;
+                if (row < r1 && col < r1) A[(long long)col * lda + row] -= acc[u][v][r];
+            }
+    if (a == b) {
+        for (int idx = tid; idx < 64 * 64; idx += 256) {
+            const int c = idx >> 6, r = idx & 63;
+            if (I + r < r1 && c < jb) Lo[(long long)(j + c) * ldo + I + r] = S1[r][c];
+        }
+        if (rhs && tid < 64 && I + tid < r1) {
+            double acc1 = 0.0;
+            for (int c = 0; c < jb; ++c) acc1 += S1[tid][c] * yj[c];
+            rhs[I + tid] -= acc1;
+        }
+    }
 }
 
-void rhs_update(hipStream_t st, const double* L, int ld, int j, int jb, int r0, int r1, double* r)
+void envelope_step(hipStream_t st, double* A, int lda, long long sA, double* Lo, int ldo,
+                   long long sLo, int j, int jb, const double* Dinv, long long sD, int r1,
+                   double* rhs, long long sR, int batch)
 {
-    if (r1 <= r0) return;
-    hipLaunchKernelGGL(rhs_update_kernel, dim3((r1 - r0 + 255) / 256), dim3(256), 0, st, L, ld, j, jb,
-                       r0, r1, r);
+    const int rows = r1 - j - jb;
+    if (rows <= 0) return;
+    const int nt = (rows + 63) / 64;
+    hipLaunchKernelGGL(envelope_step_kernel, dim3(nt * (nt + 1) / 2, batch), dim3(256), 0, st, A, lda,
+                       sA, Lo, ldo, sLo, j, jb, Dinv, sD, r1, rhs, sR);
+}
+
+// Backward substitution L^T u = y over one block row of up to 256 rows
+// [j0, j0 + br): every workgroup solves the block's four 64-row sub-blocks in
+// turn (using their diagonal inverses and the L tiles inside the block), then
+// updates y_K -= L_{block,K}^T u_block for its share of the columns
+// K in [kbeg, j0) (one wave per column, lanes along the rows).
+__global__ __launch_bounds__(256) void trsv_lt_block_kernel(const double* L, int ld, long long sL,
+                                                            int j0, int br, int kbeg,
+                                                            const double* Dinv, long long sD,
+                                                            double* y, double* u, long long sY)
+{
+    {
+        const long long zb = blockIdx.y;
+        L += zb * sL;
+        Dinv += zb * sD;
+        y += zb * sY;
+        u += zb * sY;
+    }
+    __shared__ double yb[256], ub[256];
+    const int tid = threadIdx.x;
+    yb[tid] = tid < br ? y[j0 + tid] : 0.0;
+    ub[tid] = 0.0;
+    __syncthreads();
+    const int nsub = (br + 63) / 64;
+    for (int sb = nsub - 1; sb >= 0; --sb) {
+        const int s0 = 64 * sb, sl = (br - s0) < 64 ? (br - s0) : 64;
+        // y_sb -= sum over later sub-blocks of L[later, sb]^T u_later: one wave
+        // per column of the sub-block, lanes along the (contiguous) rows
+        if (s0 + 64 < br) {
+            const int ln = tid & 63;
+            for (int t = tid >> 6; t < sl; t += 4) {
+                const double* colp = L + (long long)(j0 + s0 + t) * ld + j0;
+                double v = 0.0;
+                for (int r = s0 + 64 + ln; r < br; r += 64) v += colp[r] * ub[r];
+                v = wave_sum(v);
+                if (ln == 0) yb[s0 + t] -= v;
+            }
+            __syncthreads();
+        }
+        if (tid < sl) {
+            const double* D = Dinv + (long long)((j0 + s0) / 64) * 64 * 64;
+            double acc = 0.0;
+            for (int i = tid; i < sl; ++i) acc += D[tid * 64 + i] * yb[s0 + i];
+            ub[s0 + tid] = acc;
+        }
+        __syncthreads();
+    }
+    if (blockIdx.x == 0 && tid < br) u[j0 + tid] = ub[tid];
+    const int lane = tid & 63;
+    const int wave = blockIdx.x * 4 + (tid >> 6);
+    const int nwave = gridDim.x * 4;
+    for (int kcol = kbeg + wave; kcol < j0; kcol += nwave) {
+        const double* colp = L + (long long)kcol * ld + j0;
+        double v = 0.0;
+        for (int r = lane; r < br; r += 64) v += colp[r] * ub[r];
+        v = wave_sum(v);
+        if (lane == 0) y[kcol] -= v;
+    }
+}
+
+void trsv_lower_t_block(hipStream_t st, const double* L, int ld, long long sL, int j0, int br,
+                        int kbeg, const double* Dinv, long long sD, double* y, double* u,
+                        long long sY, int batch)
+{
+    int nb = (j0 - kbeg + 7) / 8;   // about two columns per wave
+    nb = nb < 1 ? 1 : (nb > 1024 ? 1024 : nb);
+    hipLaunchKernelGGL(trsv_lt_block_kernel, dim3(nb, batch), dim3(256), 0, st, L, ld, sL, j0, br, kbeg,
+                       Dinv, sD, y, u, sY);
 }
 
 __global__ void save_diag_kernel(const double* A, int lda, long long sA, int n, double* d,
@@ -551,11 +799,13 @@ void copy_row(hipStream_t st, const double* src, int lsrc, long long sS, double*
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void schur_mblocks_kernel(const int32_t* desc, const double* P,
                                                             int ldp, long long sP, int cbase,
-                                                            int mg, double* Mbuf)
+                                                            int mg, double* Mbuf, int ngeo)
 {
     const int blk = blockIdx.x;
+    const long long inst = blockIdx.y;
+    P += inst * ngeo * sP;
     const int32_t* d = desc + 8 * blk;
-    double* out = Mbuf + (long long)blk * mg * mg;
+    double* out = Mbuf + ((long long)gridDim.x * inst + blk) * mg * mg;
     for (int idx = threadIdx.x; idx < mg * mg; idx += blockDim.x) {
         const int r = idx % mg, c = idx / mg;
         double v = 0.0;
@@ -570,17 +820,20 @@ __global__ __launch_bounds__(256) void schur_mblocks_kernel(const int32_t* desc,
 }
 
 void schur_mblocks(hipStream_t st, int nblk, const int32_t* desc, const double* P, int ldp,
-                   long long sP, int cbase, int mg, double* Mbuf)
+                   long long sP, int cbase, int mg, double* Mbuf, int ngeo, int ninst)
 {
     if (nblk <= 0) return;
-    hipLaunchKernelGGL(schur_mblocks_kernel, dim3(nblk), dim3(256), 0, st, desc, P, ldp, sP, cbase,
-                       mg, Mbuf);
+    hipLaunchKernelGGL(schur_mblocks_kernel, dim3(nblk, ninst), dim3(256), 0, st, desc, P, ldp, sP,
+                       cbase, mg, Mbuf, ngeo);
 }
 
 __global__ void schur_avec_kernel(const int32_t* desc, const double* P, int ldp, long long sP,
-                                  int cbase, int acol, int mg, double* abuf)
+                                  int cbase, int acol, int mg, double* abuf, int ngeo)
 {
     const int e = blockIdx.x;
+    const long long inst = blockIdx.y;
+    P += inst * ngeo * sP;
+    abuf += inst * gridDim.x * (long long)mg;
     const int32_t* d = desc + 4 * e;
     for (int r = threadIdx.x; r < mg; r += blockDim.x) {
         double v = 0.0;
@@ -594,11 +847,11 @@ __global__ void schur_avec_kernel(const int32_t* desc, const double* P, int ldp,
 }
 
 void schur_avec(hipStream_t st, int nE, const int32_t* desc, const double* P, int ldp, long long sP,
-                int cbase, int acol, int mg, double* abuf)
+                int cbase, int acol, int mg, double* abuf, int ngeo, int ninst)
 {
     if (nE <= 0) return;
-    hipLaunchKernelGGL(schur_avec_kernel, dim3(nE), dim3(64), 0, st, desc, P, ldp, sP, cbase, acol,
-                       mg, abuf);
+    hipLaunchKernelGGL(schur_avec_kernel, dim3(nE, ninst), dim3(64), 0, st, desc, P, ldp, sP, cbase,
+                       acol, mg, abuf, ngeo);
 }
 
 // One workgroup per mg x mg block (E1, E2) of S:
@@ -610,11 +863,18 @@ __global__ __launch_bounds__(256) void schur_sblocks_kernel(int nE, int mg, cons
                                                             const int32_t* mdesc, const double* P,
                                                             int ldp, long long sP,
                                                             const double* Mbuf, double* S, int lds,
-                                                            const int32_t* perm)
+                                                            const int32_t* perm, int ngeo,
+                                                            long long sM, long long sS)
 {
     __shared__ double M1[64 * 64];
     __shared__ double M2[64 * 64];
     const int E1 = blockIdx.x, E2 = blockIdx.y;
+    {
+        const long long inst = blockIdx.z;
+        P += inst * ngeo * sP;
+        Mbuf += inst * sM;
+        S += inst * sS;
+    }
     const int blk = E1 + E2 * nE;
     const int mm = mg * mg;
     const int tid = threadIdx.x;
@@ -667,20 +927,29 @@ __global__ __launch_bounds__(256) void schur_sblocks_kernel(int nE, int mg, cons
 
 void schur_sblocks(hipStream_t st, int nE, int mg, const int32_t* tptr, const int32_t* tdesc,
                    const int32_t* mptr, const int32_t* mdesc, const double* P, int ldp,
-                   long long sP, const double* Mbuf, double* S, int lds, const int32_t* perm)
+                   long long sP, const double* Mbuf, double* S, int lds, const int32_t* perm,
+                   int ngeo, long long sM, long long sS, int ninst)
 {
     if (nE <= 0) return;
-    hipLaunchKernelGGL(schur_sblocks_kernel, dim3(nE, nE), dim3(256), 0, st, nE, mg, tptr, tdesc,
-                       mptr, mdesc, P, ldp, sP, Mbuf, S, lds, perm);
+    hipLaunchKernelGGL(schur_sblocks_kernel, dim3(nE, nE, ninst), dim3(256), 0, st, nE, mg, tptr,
+                       tdesc, mptr, mdesc, P, ldp, sP, Mbuf, S, lds, perm, ngeo, sM, sS);
 }
 
 // rhs_E = sum_s q_s(E) - sum_g M_{g,E}^T a_g.
 __global__ void schur_rhs_kernel(int mg, const int32_t* qdesc, const int32_t* gptr,
                                  const int32_t* gdesc, const double* P, int ldp, long long sP,
                                  int qcol, const double* Mbuf, const double* abuf, double* rhs,
-                                 int inc, const int32_t* perm)
+                                 int inc, const int32_t* perm, int ngeo, long long sM,
+                                 long long sA, long long sR)
 {
     const int E = blockIdx.x;
+    {
+        const long long inst = blockIdx.y;
+        P += inst * ngeo * sP;
+        Mbuf += inst * sM;
+        abuf += inst * sA;
+        rhs += inst * sR;
+    }
     const int mm = mg * mg;
     const int32_t* q = qdesc + 4 * E;
     for (int r = threadIdx.x; r < mg; r += blockDim.x) {
@@ -703,54 +972,12 @@ __global__ void schur_rhs_kernel(int mg, const int32_t* qdesc, const int32_t* gp
 
 void schur_rhs(hipStream_t st, int nE, int mg, const int32_t* qdesc, const int32_t* gptr,
                const int32_t* gdesc, const double* P, int ldp, long long sP, int qcol,
-               const double* Mbuf, const double* abuf, double* rhs, int inc, const int32_t* perm)
+               const double* Mbuf, const double* abuf, double* rhs, int inc, const int32_t* perm,
+               int ngeo, long long sM, long long sA, long long sR, int ninst)
 {
     if (nE <= 0) return;
-    hipLaunchKernelGGL(schur_rhs_kernel, dim3(nE), dim3(64), 0, st, mg, qdesc, gptr, gdesc, P, ldp,
-                       sP, qcol, Mbuf, abuf, rhs, inc, perm);
-}
-
-// ---------------------------------------------------------------------------
-// One block step of the backward solve L^T u = y (L lower, blocked by 64):
-// u_J = Dinv_J^T y_J, then y_K -= L_{J,K}^T u_J for every K < J.  Every
-// workgroup recomputes u_J from the unchanged y_J, so the launch needs no
-// inter-workgroup ordering.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void trsv_lt_step_kernel(const double* L, int ld, int j0, int jb,
-                                                           int kbeg, const double* Dinv, double* y,
-                                                           double* u)
-{
-    __shared__ double yj[64], uj[64];
-    const int tid = threadIdx.x;
-    if (tid < 64) yj[tid] = tid < jb ? y[j0 + tid] : 0.0;
-    __syncthreads();
-    if (tid < 64) {
-        double s = 0.0;
-        for (int i = tid; i < jb; ++i) s += Dinv[tid * 64 + i] * yj[i];
-        uj[tid] = s;
-    }
-    __syncthreads();
-    if (blockIdx.x == 0 && tid < jb) u[j0 + tid] = uj[tid];
-    // one wave per column K < j0: lanes run over the 64 rows of block row J
-    const int lane = tid & 63;
-    const int wave = blockIdx.x * 4 + (tid >> 6);
-    const int nwave = gridDim.x * 4;
-    const double ul = lane < jb ? uj[lane] : 0.0;
-    for (int kcol = kbeg + wave; kcol < j0; kcol += nwave) {
-        double v = lane < jb ? L[(long long)kcol * ld + j0 + lane] * ul : 0.0;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-        if (lane == 0) y[kcol] -= v;
-    }
-}
-
-void trsv_lower_t_step(hipStream_t st, const double* L, int ld, int j0, int jb, int kbeg,
-                       const double* Dinv, double* y, double* u)
-{
-    int nb = (j0 - kbeg + 15) / 16;   // about 4 columns per wave
-    nb = nb < 1 ? 1 : (nb > 1024 ? 1024 : nb);
-    hipLaunchKernelGGL(trsv_lt_step_kernel, dim3(nb), dim3(256), 0, st, L, ld, j0, jb, kbeg, Dinv, y,
-                       u);
+    hipLaunchKernelGGL(schur_rhs_kernel, dim3(nE, ninst), dim3(64), 0, st, mg, qdesc, gptr, gdesc, P,
+                       ldp, sP, qcol, Mbuf, abuf, rhs, inc, perm, ngeo, sM, sA, sR);
 }
 
 // ---------------------------------------------------------------------------
@@ -758,27 +985,22 @@ void trsv_lower_t_step(hipStream_t st, const double* L, int ld, int j0, int jb, 
 // with R^{-1} = Linv1^T Linv2^T Linv3^T from the three CholeskyQR passes.
 // One wave per output entry, lanes along the contiguous column: coalesced.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
 // v[s][col] = h_s[col] + sum_i Q_Gamma[i][col] u[gidx_s[i]]
 __global__ __launch_bounds__(256) void bs_rhs_kernel(int n, int kpad, const double* X, int ldx,
                                                      long long sX, int mI, int hrow,
                                                      const int32_t* gidx, const double* u,
-                                                     double* v)
+                                                     double* v, int ngeo, long long nG)
 {
     const int s = blockIdx.y;
+    const int sg = s % ngeo;
+    u += (s / ngeo) * nG;
     const int lane = threadIdx.x & 63;
     const int col = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (col >= n) return;
     const double* xc = X + s * sX + (long long)col * ldx;
     double acc = 0.0;
     for (int i = lane; i < kpad; i += 64) {
-        const int gi = gidx[s * kpad + i];
+        const int gi = gidx[sg * kpad + i];
         if (gi >= 0) acc += xc[mI + i] * u[gi];
     }
     acc = wave_sum(acc);
@@ -801,14 +1023,14 @@ __global__ __launch_bounds__(256) void trmv_t_kernel(int n, const double* Li, in
     if (lane == 0) out[(long long)s * n + i] = acc;
 }
 
-void local_backsolve(hipStream_t st, int N, int n, int kpad, const double* X, int ldx, long long sX,
-                     int mI, int hrow, const int32_t* gidx, const double* u, const double* Linv1,
-                     const double* Linv2, const double* Linv3, int ldg, long long sG, double* c,
-                     double* tmp1, double* tmp2)
+void local_backsolve(hipStream_t st, int N, int ngeo, long long nG, int n, int kpad, const double* X,
+                     int ldx, long long sX, int mI, int hrow, const int32_t* gidx, const double* u,
+                     const double* Linv1, const double* Linv2, const double* Linv3, int ldg,
+                     long long sG, double* c, double* tmp1, double* tmp2)
 {
     dim3 grid((n + 3) / 4, N);
     hipLaunchKernelGGL(bs_rhs_kernel, grid, dim3(256), 0, st, n, kpad, X, ldx, sX, mI, hrow, gidx, u,
-                       tmp1);
+                       tmp1, ngeo, nG);
     hipLaunchKernelGGL(trmv_t_kernel, grid, dim3(256), 0, st, n, Linv3, ldg, sG, tmp1, tmp2);
     hipLaunchKernelGGL(trmv_t_kernel, grid, dim3(256), 0, st, n, Linv2, ldg, sG, tmp2, tmp1);
     hipLaunchKernelGGL(trmv_t_kernel, grid, dim3(256), 0, st, n, Linv1, ldg, sG, tmp1, c);
@@ -817,17 +1039,20 @@ void local_backsolve(hipStream_t st, int N, int n, int kpad, const double* X, in
 // u[E*mg + r] = up[perm[E]*mg + r]
 __global__ void unpermute_kernel(int nE, int mg, const int32_t* perm, const double* up, double* u)
 {
+    const long long n = (long long)nE * mg;
+    const long long inst = blockIdx.y;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= nE * mg) return;
+    if (idx >= n) return;
     const int E = idx / mg, r = idx % mg;
-    u[idx] = up[(long long)perm[E] * mg + r];
+    u[inst * n + idx] = up[inst * n + (long long)perm[E] * mg + r];
 }
 
-void unpermute(hipStream_t st, int nE, int mg, const int32_t* perm, const double* up, double* u)
+void unpermute(hipStream_t st, int nE, int mg, const int32_t* perm, const double* up, double* u,
+               int ninst)
 {
     if (nE <= 0) return;
-    hipLaunchKernelGGL(unpermute_kernel, dim3((nE * mg + 255) / 256), dim3(256), 0, st, nE, mg, perm,
-                       up, u);
+    hipLaunchKernelGGL(unpermute_kernel, dim3((nE * mg + 255) / 256, ninst), dim3(256), 0, st, nE, mg,
+                       perm, up, u);
 }
 
 // Dense S in the original interface order from the permuted copy (ld lds).

@@ -19,7 +19,7 @@ void blocked_potrf(hipStream_t st, double* A, int lda, long long sA, int Mrows, 
         const int jb = std::min(NB, n - j);
         double* Dj = Dinv + (long long)(j / NB) * NB * NB;
         potrf_diag(st, A, lda, sA, j, jb, Dj, sD, Linv, ldl, sL, info, pass, batch, dsave, sS, tau,
-                   nullptr);
+                   nullptr, 0);
         const int Mb = Mrows - j - jb;
         if (Mb > 0) {
             double* panel = A + (long long)j * lda + (j + jb);
@@ -42,25 +42,19 @@ void blocked_potrf(hipStream_t st, double* A, int lda, long long sA, int Mrows, 
     }
 }
 
-void envelope_potrf(hipStream_t st, double* A, int lda, int n, const int* rend, double* Dinv,
-                    DevInfo* info, int pass, double* dsave, double* rhs)
+void envelope_potrf(hipStream_t st, double* A, int lda, long long sA, double* Lo, int ldo,
+                    long long sLo, int n, const int* rend, double* Dinv, long long sD, DevInfo* info,
+                    int pass, double* dsave, double* rhs, long long sR, int batch)
 {
     const double tau = 64.0 * n * 0x1p-53;
-    if (dsave) save_diag(st, A, lda, 0, n, dsave, 0, 1);
+    if (dsave) save_diag(st, A, lda, sA, n, dsave, n, batch);
     for (int j = 0, p = 0; j < n; j += NB, ++p) {
         const int jb = std::min(NB, n - j);
         double* Dj = Dinv + (long long)p * NB * NB;
-        potrf_diag(st, A, lda, 0, j, jb, Dj, 0, nullptr, 0, 0, info, pass, 1, dsave, 0, tau, rhs);
-        const int r1 = std::min(n, rend[p]);
-        const int Mb = r1 - j - jb;
-        if (Mb > 0) {
-            double* panel = A + (long long)j * lda + (j + jb);
-            gemm_f64(st, false, true, 0, false, Mb, jb, jb, 1.0, panel, lda, 0, Dj, NB, 0, 0.0, panel,
-                     lda, 0, 1);
-            if (rhs) rhs_update(st, A, lda, j, jb, j + jb, r1, rhs);
-            gemm_f64(st, false, true, 0, true, Mb, Mb, jb, -1.0, panel, lda, 0, panel, lda, 0, 1.0,
-                     A + (long long)(j + jb) * lda + (j + jb), lda, 0, 1);
-        }
+        potrf_diag(st, A, lda, sA, j, jb, Dj, sD, nullptr, 0, 0, info, pass, batch, dsave, n, tau, rhs,
+                   sR);
+        envelope_step(st, A, lda, sA, Lo, ldo, sLo, j, jb, Dj, sD, std::min(n, rend[p]), rhs, sR,
+                      batch);
     }
 }
 

@@ -37,6 +37,8 @@ struct EdgeOwner {
 
 struct elmddm_plan {
     elmddm_problem p{};
+    int B = 1;    // problem instances per solve (same geometry)
+    int NT = 0;   // subdomains over all instances, B * N
     int N = 0, n = 0, nx = 0, ny = 0, q2 = 0, mg = 0, mb = 0;
     int maxb = 0, maxk = 0, max_rows = 0;
     int mI = 0, kpad = 0, hrow = 0, dbase = 0, ldx = 0, gram_rows = 0, ldg = 0, ldp = 0;
@@ -55,7 +57,7 @@ struct elmddm_plan {
     double *X0 = nullptr, *X1 = nullptr, *G = nullptr, *Linv[3] = {nullptr, nullptr, nullptr};
     double *Dinv = nullptr, *Tbuf = nullptr, *P = nullptr, *Mbuf = nullptr, *abuf = nullptr;
     double *Sx = nullptr, *Skeep = nullptr, *DinvS = nullptr, *yvec = nullptr, *dsave = nullptr;
-    double *uperm = nullptr, *bs1 = nullptr, *bs2 = nullptr;
+    double *uperm = nullptr, *bs1 = nullptr, *bs2 = nullptr, *SL = nullptr;
     int32_t* d_perm = nullptr;
     std::vector<int> rend;   // per 64-panel of S: one past the last row of the envelope
     std::vector<int> kbeg;   // per 64-block row of S: first column reaching it
@@ -183,6 +185,7 @@ elmddm_status build(elmddm_plan* P)
     P->nx = nx;
     P->ny = ny;
     P->N = nx * ny;
+    P->NT = P->B * P->N;
     P->n = p.neurons;
     P->q2 = p.q_x * p.q_y;
     P->mg = p.m_ifc_edge;
@@ -476,29 +479,35 @@ elmddm_status build(elmddm_plan* P)
     TRY(P->upload(&P->d_gptr, gptr));
     TRY(P->upload(&P->d_gdesc, gdesc));
     TRY(P->upload(&P->d_perm, perm));
-    TRY(P->dalloc(&P->X0, (size_t)N * P->sX));
-    TRY(P->dalloc(&P->X1, (size_t)N * P->sX));
-    TRY(P->dalloc(&P->G, (size_t)N * P->sG));
-    for (int i = 0; i < 3; ++i) TRY(P->dalloc(&P->Linv[i], (size_t)N * P->sL));
-    TRY(P->dalloc(&P->Dinv, (size_t)N * P->sD));
-    TRY(P->dalloc(&P->Tbuf, (size_t)N * NB * n));
-    TRY(P->dalloc(&P->P, (size_t)N * P->sP));
-    TRY(P->dalloc(&P->Mbuf, (size_t)std::max(P->n_mblocks, 1) * mg * mg));
-    TRY(P->dalloc(&P->abuf, (size_t)std::max(P->nE, 1) * mg));
-    TRY(P->dalloc(&P->Sx, (size_t)P->lds * std::max(P->nG, 1)));
-    TRY(P->dalloc(&P->DinvS, (size_t)std::max(P->nblkS, 1) * NB * NB));
-    TRY(P->dalloc(&P->yvec, (size_t)std::max(P->nG, 1)));
-    TRY(P->dalloc(&P->dsave, std::max((size_t)N * n, (size_t)std::max(P->nG, 1))));
-    TRY(P->dalloc(&P->uperm, (size_t)std::max(P->nG, 1)));
-    TRY(P->dalloc(&P->bs1, (size_t)N * n));
-    TRY(P->dalloc(&P->bs2, (size_t)N * n));
+    const size_t NT = (size_t)P->NT, Bn = (size_t)P->B;
+    const size_t nGm = (size_t)std::max(P->nG, 1);
+    TRY(P->dalloc(&P->X0, NT * P->sX));
+    TRY(P->dalloc(&P->X1, NT * P->sX));
+    TRY(P->dalloc(&P->G, NT * P->sG));
+    for (int i = 0; i < 3; ++i) TRY(P->dalloc(&P->Linv[i], NT * P->sL));
+    TRY(P->dalloc(&P->Dinv, NT * P->sD));
+    TRY(P->dalloc(&P->Tbuf, NT * NB * n));
+    TRY(P->dalloc(&P->P, NT * P->sP));
+    TRY(P->dalloc(&P->Mbuf, Bn * std::max(P->n_mblocks, 1) * mg * mg));
+    TRY(P->dalloc(&P->abuf, Bn * std::max(P->nE, 1) * mg));
+    TRY(P->dalloc(&P->Sx, Bn * P->lds * nGm));
+    TRY(P->dalloc(&P->DinvS, Bn * std::max(P->nblkS, 1) * NB * NB));
+    TRY(P->dalloc(&P->yvec, Bn * nGm));
+    TRY(P->dalloc(&P->dsave, std::max(NT * n, Bn * nGm)));
+    TRY(P->dalloc(&P->uperm, Bn * nGm));
+    TRY(P->dalloc(&P->SL, Bn * P->lds * nGm));
+    TRY(P->dalloc(&P->bs1, NT * n));
+    TRY(P->dalloc(&P->bs2, NT * n));
     TRY(P->dalloc(&P->d_info, 1));
     // The strictly upper parts of the inverse factors are never written by the
     // solve and must read as zero.
     for (int i = 0; i < 3; ++i)
-        if (hipMemset(P->Linv[i], 0, (size_t)N * P->sL * sizeof(double)) != hipSuccess)
+        if (hipMemset(P->Linv[i], 0, NT * P->sL * sizeof(double)) != hipSuccess)
             return fail(ELMDDM_HIP_ERROR, "hipMemset failed during plan creation");
-    if (hipMemset(P->X1, 0, (size_t)N * P->sX * sizeof(double)) != hipSuccess)
+    // Entries of the interface factor outside the envelope are never written and read as zero.
+    if (hipMemset(P->SL, 0, Bn * P->lds * nGm * sizeof(double)) != hipSuccess)
+        return fail(ELMDDM_HIP_ERROR, "hipMemset failed during plan creation");
+    if (hipMemset(P->X1, 0, NT * P->sX * sizeof(double)) != hipSuccess)
         return fail(ELMDDM_HIP_ERROR, "hipMemset failed during plan creation");
 #undef TRY
     return ELMDDM_OK;
@@ -540,13 +549,22 @@ extern "C" {
 
 elmddm_status elmddm_plan_create(const elmddm_problem* problem, elmddm_plan** plan)
 {
+    return elmddm_plan_create_batch(problem, 1, plan);
+}
+
+elmddm_status elmddm_plan_create_batch(const elmddm_problem* problem, int32_t batch,
+                                       elmddm_plan** plan)
+{
     if (!plan) return fail(ELMDDM_INVALID_ARG, "plan output pointer is NULL");
     *plan = nullptr;
     elmddm_status st = validate(problem);
     if (st != ELMDDM_OK) return st;
+    if (batch < 1 || (int64_t)batch * problem->nsub_x * problem->nsub_y > (1 << 20))
+        return fail(ELMDDM_INVALID_ARG, "batch must be >= 1 and batch * nsub <= 2^20");
     elmddm_plan* P = new (std::nothrow) elmddm_plan();
     if (!P) return fail(ELMDDM_OOM, "host allocation failed");
     P->p = *problem;
+    P->B = batch;
     try {
         st = build(P);
     } catch (const std::bad_alloc&) {
@@ -573,6 +591,7 @@ elmddm_status elmddm_plan_sizes(const elmddm_plan* P, elmddm_sizes* s)
 {
     if (!P || !s) return fail(ELMDDM_INVALID_ARG, "NULL argument");
     s->nsub = P->N;
+    s->batch = P->B;
     s->neurons = P->n;
     s->n_interior = P->q2;
     s->n_interface = P->nG;
@@ -604,8 +623,8 @@ elmddm_status elmddm_assemble(elmddm_plan* P, const double* W, const double* b, 
     if (P->nB > 0 && !g) return fail(ELMDDM_INVALID_ARG, "g is NULL but the problem has boundary points");
     if (P->p.op == ELMDDM_OP_VARCOEF && !coef) return fail(ELMDDM_INVALID_ARG, "coef is NULL for VARCOEF");
     hipStream_t st = (hipStream_t)stream;
-    assemble(st, P->N, P->ldx, P->n, row_table(P), sub_geom(P), P->p.op, W, b, f, g, coef, P->q2,
-             nullptr, F, P->max_rows, K, P->max_rows, A, std::max(P->maxk, 1));
+    assemble(st, P->NT, P->N, P->nB, P->ldx, P->n, row_table(P), sub_geom(P), P->p.op, W, b, f, g,
+             coef, P->q2, nullptr, F, P->max_rows, K, P->max_rows, A, std::max(P->maxk, 1));
     return check_launch("assemble");
 }
 
@@ -629,7 +648,7 @@ elmddm_status elmddm_get_schur(elmddm_plan* P, double* S, double* rhs, void* str
     // The kept copy is in the permuted edge order: S in the first nG rows, rhs in row nG.
     unpermute_matrix(st, P->nE, P->mg, P->d_perm, P->Skeep, P->lds, S);
     copy_row(st, P->Skeep + P->nG, P->lds, 0, P->uperm, 1, 0, P->nG, 1);
-    unpermute(st, P->nE, P->mg, P->d_perm, P->uperm, rhs);
+    unpermute(st, P->nE, P->mg, P->d_perm, P->uperm, rhs, 1);
     return check_launch("get_schur");
 }
 
@@ -645,13 +664,15 @@ elmddm_status elmddm_solve(elmddm_plan* P, const double* W, const double* b, con
     if (P->timing) P->harvest();
     P->last_stream = st;
     P->solved = true;
-    const int N = P->N, n = P->n, ldx = P->ldx, ldg = P->ldg;
+    const int N = P->NT, n = P->n, ldx = P->ldx, ldg = P->ldg;
+    const int B = P->B;
+    const long long sS = (long long)P->lds * std::max(P->nG, 1);
     init_info(st, P->d_info);
     P->mark(0, st);
 
     // Feature assembly: X0 = [K rows | interface rows | flux rows], column n = F.
-    assemble(st, N, ldx, n, row_table(P), sub_geom(P), P->p.op, W, b, f, g, coef, P->q2, P->X0,
-             nullptr, 0, nullptr, 0, nullptr, 0);
+    assemble(st, N, P->N, P->nB, ldx, n, row_table(P), sub_geom(P), P->p.op, W, b, f, g, coef, P->q2,
+             P->X0, nullptr, 0, nullptr, 0, nullptr, 0);
     P->mark(1, st);
 
     // Three-pass shifted CholeskyQR of every K^s (Fukaya et al., SIAM J. Sci.
@@ -690,12 +711,14 @@ elmddm_status elmddm_solve(elmddm_plan* P, const double* W, const double* b, con
         gemm_f64(st, false, true, 0, false, 2 * P->kpad + 16, P->kpad + 1, n, 1.0, dst + P->mI, ldx,
                  P->sX, dst + P->mI, ldx, P->sX, 0.0, P->P, P->ldp, P->sP, N);
         const int cbase = P->kpad + 16;
-        schur_mblocks(st, P->n_mblocks, P->d_mdesc, P->P, P->ldp, P->sP, cbase, P->mg, P->Mbuf);
-        schur_avec(st, P->nE, P->d_adesc, P->P, P->ldp, P->sP, cbase, P->kpad, P->mg, P->abuf);
+        const long long sM = (long long)P->n_mblocks * P->mg * P->mg;
+        schur_mblocks(st, P->n_mblocks, P->d_mdesc, P->P, P->ldp, P->sP, cbase, P->mg, P->Mbuf, P->N, B);
+        schur_avec(st, P->nE, P->d_adesc, P->P, P->ldp, P->sP, cbase, P->kpad, P->mg, P->abuf, P->N, B);
         schur_sblocks(st, P->nE, P->mg, P->d_tptr, P->d_tdesc, P->d_mptr, P->d_mlist, P->P, P->ldp,
-                      P->sP, P->Mbuf, P->Sx, P->lds, P->d_perm);
+                      P->sP, P->Mbuf, P->Sx, P->lds, P->d_perm, P->N, sM, sS, B);
         schur_rhs(st, P->nE, P->mg, P->d_qdesc, P->d_gptr, P->d_gdesc, P->P, P->ldp, P->sP, P->kpad,
-                  P->Mbuf, P->abuf, P->yvec, 1, P->d_perm);
+                  P->Mbuf, P->abuf, P->yvec, 1, P->d_perm, P->N, sM, (long long)P->nE * P->mg,
+                  P->nG, B);
         P->mark(5, st);
         if (P->keep_schur && P->Skeep) {
             (void)hipMemcpyAsync(P->Skeep, P->Sx, (size_t)P->lds * P->nG * sizeof(double),
@@ -706,16 +729,17 @@ elmddm_status elmddm_solve(elmddm_plan* P, const double* W, const double* b, con
         // Interface solve in the permuted order: envelope Cholesky with the
         // forward substitution fused (yvec <- L^{-1} rhs), then L^T u = y
         // block by block, then back to the interface numbering.
-        envelope_potrf(st, P->Sx, P->lds, P->nG, P->rend.data(), P->DinvS, P->d_info, 4, P->dsave,
-                       P->yvec);
+        const long long sDS = (long long)P->nblkS * NB * NB;
+        envelope_potrf(st, P->Sx, P->lds, sS, P->SL, P->lds, sS, P->nG, P->rend.data(), P->DinvS, sDS,
+                       P->d_info, 4, P->dsave, P->yvec, P->nG, B);
         P->mark(6, st);
-        for (int pb = P->nblkS - 1; pb >= 0; --pb) {
-            const int jb0 = pb * NB;
-            const int jb = std::min(NB, P->nG - jb0);
-            trsv_lower_t_step(st, P->Sx, P->lds, jb0, jb, P->kbeg[pb],
-                              P->DinvS + (long long)pb * NB * NB, P->yvec, P->uperm);
+        const int BR = 4 * NB;
+        for (int j0 = (P->nG - 1) / BR * BR; j0 >= 0; j0 -= BR) {
+            const int br = std::min(BR, P->nG - j0);
+            trsv_lower_t_block(st, P->SL, P->lds, sS, j0, br, P->kbeg[j0 / NB], P->DinvS, sDS,
+                               P->yvec, P->uperm, P->nG, B);
         }
-        unpermute(st, P->nE, P->mg, P->d_perm, P->uperm, u_gamma);
+        unpermute(st, P->nE, P->mg, P->d_perm, P->uperm, u_gamma, B);
         est = check_launch("interface solve");
         if (est != ELMDDM_OK) return est;
     } else {
@@ -723,12 +747,12 @@ elmddm_status elmddm_solve(elmddm_plan* P, const double* W, const double* b, con
         P->mark(6, st);
     }
     P->mark(7, st);
-    local_backsolve(st, N, n, P->kpad, dst, ldx, P->sX, P->mI, P->hrow, P->d_gidx, u_gamma,
+    local_backsolve(st, N, P->N, P->nG, n, P->kpad, dst, ldx, P->sX, P->mI, P->hrow, P->d_gidx, u_gamma,
                     P->Linv[0], P->Linv[1], P->Linv[2], ldg, P->sL, c, P->bs1, P->bs2);
     const long long nc = (long long)N * n;
     P->mark(8, st);
     check_finite(st, c, nc, P->d_info);
-    if (P->nG > 0) check_finite(st, u_gamma, (long long)P->nG, P->d_info);
+    if (P->nG > 0) check_finite(st, u_gamma, (long long)B * P->nG, P->d_info);
     if (P->timing) P->ev_pending = true;
     return check_launch("back-solve");
 }
@@ -742,9 +766,9 @@ elmddm_status elmddm_solve_info(elmddm_plan* P, elmddm_info* info)
     if (hipMemcpy(&h, P->d_info, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess)
         return check_launch("solve_info copy");
     info->status = h.status;
-    info->bad_subdomain = h.bad_subdomain == INT_MAX ? -1 : h.bad_subdomain;
+    info->bad_subdomain = h.bad_subdomain == INT_MAX ? -1 : h.bad_subdomain % P->N;
     info->bad_pass = h.bad_pass;
-    info->reserved = 0;
+    info->bad_instance = h.bad_subdomain == INT_MAX ? -1 : h.bad_subdomain / P->N;
     return ELMDDM_OK;
 }
 

@@ -36,6 +36,8 @@ int elmddm_test_gemm(int ta, int tb, int kmode, int lower, int M, int N, int K, 
     return hipGetLastError() == hipSuccess ? 0 : 7;
 }
 
+void elmddm_test_set_gemm_variant(int which, int v) { set_gemm_variant(which, v); }
+
 // info: device int32[4] (status, bad_subdomain, bad_pass, pad), initialised by the caller.
 int elmddm_test_potrf(double* A, int lda, long long sA, int Mrows, int n, double* Dinv,
                       long long sD, double* Linv, int ldl, long long sL, double* Tbuf, int* info,
