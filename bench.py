@@ -67,6 +67,7 @@ def main():
     du = torch.zeros(nb * s.n_interface, dtype=torch.float64, device=dev)
     dc = torch.zeros(nb * s.nsub * s.neurons, dtype=torch.float64, device=dev)
 
+    tuned = plan.autotune()
     for i in range(args.warmup):
         W, b = inst[i % len(inst)]
         plan.solve(W, b, df, dg, None, du, dc)
@@ -131,14 +132,15 @@ def main():
 
     # Roofline of the dominant kernel: the batched FP64 MFMA Gram (SYRK)
     # launch.  Algorithmic work per launch: sum over subdomains of
-    # m_s * c * (c + 1) flops for the c = n (passes 1-2) or n + 1 (pass 3)
-    # columns of the Gram matrix (symmetric product, lower triangle).
+    # m_s * n * (n + 1) flops (symmetric product, lower triangle); the third
+    # CholeskyQR pass adds the right-hand-side row, 2 m_s n flops.
     m_rows = P.q_x * P.q_y + 4 * P.m_ifc_edge if P.m_ifc_edge == P.m_bdry_edge else s.max_rows
     n = P.neurons
-    flops_per_solve = P.nsub * m_rows * (2 * n * (n + 1) + (n + 1) * (n + 2))
+    flops_per_solve = P.nsub * m_rows * (3 * n * (n + 1) + 2 * n)
     gram_ms = stage_ms[1] / max(nsolved, 1) / 3.0
     achieved = nb * flops_per_solve / 3.0 / (gram_ms * 1e-3) / 1e12 if gram_ms > 0 else 0.0
-    roofline = {"bound": "mfma", "kernel": "gram_syrk (gemm_f64_kernel<true,false,0,true>)",
+    kname = ("gemm_strip_kernel<T=%d>" % tuned[0]) if tuned[0] >= 4 else ("gemm_f64_kernel variant %d" % (-1 - tuned[0]))
+    roofline = {"bound": "mfma", "kernel": "gram product, " + kname,
                 "achieved": achieved, "peak": MFMA_F64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / MFMA_F64_PEAK_TFLOPS, "traffic": None,
                 "avg_launch_ms": gram_ms}
@@ -161,7 +163,7 @@ def main():
         "config": {"workload": "2D Poisson 8x8 subdomains, 400 tanh neurons each (U[-4,4]), "
                                "40x40 interior points, 40 points per boundary/interface edge; plain FP64",
                    "subdomains": P.nsub, "neurons": n, "interface_unknowns": s.n_interface,
-                   "instances_per_step": nb},
+                   "instances_per_step": nb, "autotuned_kernels": tuned},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity": parity,

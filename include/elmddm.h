@@ -179,6 +179,17 @@ elmddm_status elmddm_assemble(elmddm_plan* plan, const double* W, const double* 
 elmddm_status elmddm_plan_keep_schur(elmddm_plan* plan, int32_t keep);
 elmddm_status elmddm_get_schur(elmddm_plan* plan, double* S, double* rhs, void* stream);
 
+/* Time the candidate kernels for the two large local products (the Gram
+ * matrices of the CholeskyQR passes and the triangular solves) on this plan's
+ * shapes and keep the fastest for later solves: the 64 x 64 tile kernel in
+ * four variants (K depth 16/32, XCD-aware tile order on/off) and the strip
+ * kernel with 16T-wide tiles, T = 4..8.  Overwrites the plan's workspace
+ * (call before a solve, not between a solve and elmddm_get_schur); runs
+ * synchronously on stream.  choice (NULL or int32[2]) receives the codes of
+ * the kernels kept: < 0 is the 64 x 64 kernel variant (-1 - code), >= 4 the
+ * strip width T. */
+elmddm_status elmddm_autotune(elmddm_plan* plan, void* stream, int32_t* choice);
+
 /* Per-stage device timing of solves (HIP events recorded on the solve's
  * stream around each stage).  When enabled, every elmddm_solve adds the
  * elapsed time of each stage to running totals; elmddm_stage_times

@@ -33,6 +33,7 @@ EXPORTED = [
     "elmddm_plan_create", "elmddm_plan_create_batch", "elmddm_plan_destroy", "elmddm_plan_sizes", "elmddm_points",
     "elmddm_solve", "elmddm_solve_info", "elmddm_eval", "elmddm_assemble",
     "elmddm_plan_keep_schur", "elmddm_get_schur", "elmddm_set_timing", "elmddm_stage_times",
+    "elmddm_autotune",
     "elmddm_status_string", "elmddm_last_error",
 ]
 
@@ -89,6 +90,7 @@ def lib():
         L.elmddm_plan_keep_schur.argtypes = [vp, i32]
         L.elmddm_get_schur.argtypes = [vp, dp, dp, vp]
         L.elmddm_set_timing.argtypes = [vp, i32]
+        L.elmddm_autotune.argtypes = [vp, vp, ctypes.POINTER(i32)]
         L.elmddm_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]
         L.elmddm_status_string.argtypes = [i32]
         L.elmddm_status_string.restype = ctypes.c_char_p
@@ -175,6 +177,12 @@ class Plan:
 
     def keep_schur(self, keep=True):
         _check(lib().elmddm_plan_keep_schur(self._h, 1 if keep else 0))
+
+    def autotune(self):
+        """Pick the fastest kernels for this plan's large products; returns their codes."""
+        ch = (ctypes.c_int32 * 2)()
+        _check(lib().elmddm_autotune(self._h, _stream(), ch))
+        return list(ch)
 
     def set_timing(self, enable=True):
         _check(lib().elmddm_set_timing(self._h, 1 if enable else 0))

@@ -53,6 +53,26 @@ void gemm_f64(hipStream_t st, bool ta, bool tb, int kmode, bool lower, int M, in
 // bit 1 = K depth 32 instead of 16, bit 0 = XCD-aware tile order.
 void set_gemm_variant(int which, int v);
 
+// Strip-tiled MFMA products (tile 16 T x 16 T, T waves); strip_width picks T for n.
+int strip_width(int n);
+// Kernel choice for the large local products: code < 0 selects the 64 x 64
+// kernel variant (-1 - code), code >= 4 the strip kernel of that width.
+void gram_product(hipStream_t st, int code, int n, int rows, const double* X, int ldx, long long sX,
+                  double* G, int ldg, long long sG, int batch);
+void trsm_product(hipStream_t st, int code, int rows, int n, const double* X, int ldx, long long sX,
+                  const double* Linv, int ldl, long long sL, double* Y, long long sY, int batch);
+// G = X^T X (lower triangle) over `rows` rows and n columns of every X in the batch.
+void gram_strip(hipStream_t st, int T, int n, int rows, const double* X, int ldx, long long sX,
+                double* G, int ldg, long long sG, int batch);
+// Y = X Linv^T for Linv lower triangular (n x n); X, Y: rows x n, leading dimension ldx.
+void trsm_strip(hipStream_t st, int T, int rows, int n, const double* X, int ldx, long long sX,
+                const double* Linv, int ldl, long long sL, double* Y, long long sY, int batch);
+void strip_gemm_nn(hipStream_t st, int T, int M, int N, int K, const double* A, int lda,
+                   const double* B, int ldb, double* C, int ldc);
+// Row n of an extended Gram matrix: G[n][c] = X[:, c] . X[:, n] for c < n.
+void gram_rhs_row(hipStream_t st, const double* X, int ldx, long long sX, int rows, int n, double* G,
+                  int ldg, long long sG, int batch);
+
 // Writes X (plan layout, ldx rows x (n+1) columns per subdomain) or, if Kout != nullptr,
 // the compact K^s [n][ldK], A^s [n][ldD] and F^s [ldF] per subdomain.
 // N counts the subdomains of the whole batch; subdomain s has geometry s % ngeo and
@@ -77,6 +97,10 @@ void potrf_diag(hipStream_t st, double* A, int lda, long long sA, int j, int jb,
 void envelope_step(hipStream_t st, double* A, int lda, long long sA, double* Lo, int ldo,
                    long long sLo, int j, int jb, const double* Dinv, long long sD, int r1,
                    double* rhs, long long sR, int batch);
+// Panel and forward-substitution update only (L tiles to Lo); pair with a trailing GEMM.
+void envelope_panel(hipStream_t st, const double* A, int lda, long long sA, double* Lo, int ldo,
+                    long long sLo, int j, int jb, const double* Dinv, long long sD, int r1,
+                    double* rhs, long long sR, int batch);
 // Backward substitution over a block row of br <= 256 rows (four 64-row sub-blocks).
 void trsv_lower_t_block(hipStream_t st, const double* L, int ld, long long sL, int j0, int br,
                         int kbeg, const double* Dinv, long long sD, double* y, double* u,
@@ -137,7 +161,7 @@ void blocked_potrf(hipStream_t st, double* A, int lda, long long sA, int Mrows, 
 // diagonal tiles stay in A and their inverses in Dinv.
 void envelope_potrf(hipStream_t st, double* A, int lda, long long sA, double* Lo, int ldo,
                     long long sLo, int n, const int* rend, double* Dinv, long long sD, DevInfo* info,
-                    int pass, double* dsave, double* rhs, long long sR, int batch);
+                    int pass, double* dsave, double* rhs, long long sR, int batch, bool fused);
 
 void init_info(hipStream_t st, DevInfo* info);
 void check_finite(hipStream_t st, const double* v, long long count, DevInfo* info);

@@ -228,18 +228,22 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(
         const int lr = lane & 15, lk = lane >> 4;
         for (int it = 0; it < nk; ++it) {
             if (it + 1 < nk) load(kbeg + (it + 1) * GB_K);
+            double av[GB_K / 4][2], bv[GB_K / 4][2];
 #pragma unroll
             for (int ks = 0; ks < GB_K / 4; ++ks) {
                 const int k = ks * 4 + lk;
-                const double a0 = As[k][wm * 32 + lr];
-                const double a1 = As[k][wm * 32 + 16 + lr];
-                const double b0 = Bs[k][wn * 32 + lr];
-                const double b1 = Bs[k][wn * 32 + 16 + lr];
-                acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-                acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-                acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-                acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+                av[ks][0] = As[k][wm * 32 + lr];
+                av[ks][1] = As[k][wm * 32 + 16 + lr];
+                bv[ks][0] = Bs[k][wn * 32 + lr];
+                bv[ks][1] = Bs[k][wn * 32 + 16 + lr];
             }
+#pragma unroll
+            for (int ks = 0; ks < GB_K / 4; ++ks)
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+#pragma unroll
+                    for (int v = 0; v < 2; ++v)
+                        acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks][u], bv[ks][v], acc[u][v], 0, 0, 0);
             __syncthreads();
             if (it + 1 < nk) {
                 store();
@@ -319,6 +323,248 @@ void gemm_f64(hipStream_t st, bool ta, bool tb, int kmode, bool lower, int M, in
     GEMM_CASE(false, false, 1, false)
     GEMM_CASE(false, true, 2, false)
 #undef GEMM_CASE
+}
+
+// ---------------------------------------------------------------------------
+// Strip-tiled batched FP64 GEMM for the large products (Gram matrices and the
+// triangular solves of the local factorisations).  The workgroup tile is
+// (16 T) x (16 T) with T waves; wave w owns the 16 x 16T strip of rows
+// [16w, 16w + 16) as T accumulators of V_MFMA_F64_16X16X4.  T is chosen so
+// that 16 T divides the (16-rounded) neuron count: n = 400 gives T = 5 and no
+// padded columns.  In lower mode the diagonal tiles skip the strictly upper
+// 16 x 16 blocks, so a symmetric product costs only its lower triangle.
+// ---------------------------------------------------------------------------
+template <int T, bool TA, bool TB, int KMODE, bool LOWER>
+__global__ __launch_bounds__(64 * T) void gemm_strip_kernel(
+    int M, int N, int K, double alpha, const double* A, int lda, long long sA, const double* B,
+    int ldb, long long sB, double beta, double* C, int ldc, long long sC)
+{
+    constexpr int BT = 16 * T;
+    const unsigned gx = gridDim.x, gy = gridDim.y;
+    const unsigned total = gx * gy * gridDim.z;
+    const unsigned p = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const unsigned q = (total & 7u) ? p : (p & 7u) * (total >> 3) + (p >> 3);
+    const int tm = q % gx, tn = (q / gx) % gy;
+    const long long z = q / (gx * gy);
+    if (LOWER && tm < tn) return;
+    A += z * sA;
+    B += z * sB;
+    C += z * sC;
+    const int m0 = tm * BT, n0 = tn * BT;
+    int kbeg = 0, kend = K;
+    if (KMODE == 1) kbeg = n0 < K ? n0 : K;
+    if (KMODE == 2) kend = (n0 + BT) < K ? (n0 + BT) : K;
+
+    __shared__ double As[16][BT];
+    __shared__ double Bs[16][BT];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int jmax = (LOWER && tm == tn) ? w : T - 1;   // wave-uniform
+
+    v4d acc[T];
+#pragma unroll
+    for (int j = 0; j < T; ++j) acc[j] = (v4d){0.0, 0.0, 0.0, 0.0};
+    double ra[4], rb[4];
+    constexpr int RS = 4 * T;   // threads per k row in the along-row pattern
+    auto load = [&](int k0) {
+        if (!TA) {
+            const int kk = k0 + tid / RS, mm = m0 + (tid % RS) * 4;
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                ra[e] = (kk < kend && mm + e < M) ? A[(long long)kk * lda + mm + e] : 0.0;
+        } else {
+            const int mm = m0 + (tid >> 2), kk = k0 + (tid & 3) * 4;
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                ra[e] = (mm < M && kk + e < kend) ? A[(long long)mm * lda + kk + e] : 0.0;
+        }
+        if (!TB) {
+            const int nn = n0 + (tid >> 2), kk = k0 + (tid & 3) * 4;
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                rb[e] = (nn < N && kk + e < kend) ? B[(long long)nn * ldb + kk + e] : 0.0;
+        } else {
+            const int kk = k0 + tid / RS, nn = n0 + (tid % RS) * 4;
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                rb[e] = (kk < kend && nn + e < N) ? B[(long long)kk * ldb + nn + e] : 0.0;
+        }
+    };
+    auto store = [&]() {
+        if (!TA) {
+            const int k = tid / RS, m = (tid % RS) * 4;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) As[k][m + e] = ra[e];
+        } else {
+            const int m = tid >> 2, k = (tid & 3) * 4;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) As[k + e][m] = ra[e];
+        }
+        if (!TB) {
+            const int nn = tid >> 2, k = (tid & 3) * 4;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) Bs[k + e][nn] = rb[e];
+        } else {
+            const int k = tid / RS, nn = (tid % RS) * 4;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) Bs[k][nn + e] = rb[e];
+        }
+    };
+    const int nk = (kend > kbeg) ? (kend - kbeg + 15) / 16 : 0;
+    if (nk > 0) {
+        load(kbeg);
+        store();
+        __syncthreads();
+        for (int it = 0; it < nk; ++it) {
+            if (it + 1 < nk) load(kbeg + (it + 1) * 16);
+            // all operands of the stage into registers first, then the MFMAs
+            // back to back (no branches between them)
+            double av[4], bv[4][T];
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                const int k = ks * 4 + lk;
+                av[ks] = As[k][16 * w + lr];
+#pragma unroll
+                for (int j = 0; j < T; ++j) bv[ks][j] = Bs[k][16 * j + lr];
+            }
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+                for (int j = 0; j < T; ++j)
+                    acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], bv[ks][j], acc[j], 0, 0, 0);
+            __syncthreads();
+            if (it + 1 < nk) {
+                store();
+                __syncthreads();
+            }
+        }
+    }
+    const int lq = lane >> 4;
+#pragma unroll
+    for (int j = 0; j < T; ++j) {
+        if (j > jmax) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = m0 + 16 * w + 4 * r + lq;
+            const int col = n0 + 16 * j + lr;
+            if (row < M && col < N) {
+                const long long ci = (long long)col * ldc + row;
+                double v = alpha * acc[j][r];
+                if (beta != 0.0) v += beta * C[ci];
+                C[ci] = v;
+            }
+        }
+    }
+}
+
+int strip_width(int n)
+{
+    const int nb = (n + 15) / 16;
+    int best = 4, waste = 1 << 30;
+    for (int t = 4; t <= 8; ++t) {
+        const int wst = (nb + t - 1) / t * t - nb;
+        if (wst < waste || (wst == waste && t > best)) {
+            best = t;
+            waste = wst;
+        }
+    }
+    return best;
+}
+
+template <int T, bool TA, bool TB, int KMODE, bool LOWER>
+static void strip_launch(hipStream_t st, int M, int N, int K, double alpha, const double* A, int lda,
+                         long long sA, const double* B, int ldb, long long sB, double beta,
+                         double* C, int ldc, long long sC, int batch)
+{
+    dim3 grid((M + 16 * T - 1) / (16 * T), (N + 16 * T - 1) / (16 * T), batch);
+    hipLaunchKernelGGL((gemm_strip_kernel<T, TA, TB, KMODE, LOWER>), grid, dim3(64 * T), 0, st, M, N,
+                       K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+}
+
+template <bool TA, bool TB, int KMODE, bool LOWER>
+static void strip_dispatch(int T, hipStream_t st, int M, int N, int K, double alpha, const double* A,
+                           int lda, long long sA, const double* B, int ldb, long long sB,
+                           double beta, double* C, int ldc, long long sC, int batch)
+{
+    switch (T) {
+        case 4: strip_launch<4, TA, TB, KMODE, LOWER>(st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch); break;
+        case 5: strip_launch<5, TA, TB, KMODE, LOWER>(st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch); break;
+        case 6: strip_launch<6, TA, TB, KMODE, LOWER>(st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch); break;
+        case 7: strip_launch<7, TA, TB, KMODE, LOWER>(st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch); break;
+        default: strip_launch<8, TA, TB, KMODE, LOWER>(st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch); break;
+    }
+}
+
+void gram_strip(hipStream_t st, int T, int n, int rows, const double* X, int ldx, long long sX,
+                double* G, int ldg, long long sG, int batch)
+{
+    if (n <= 0 || batch <= 0) return;
+    strip_dispatch<true, false, 0, true>(T, st, n, n, rows, 1.0, X, ldx, sX, X, ldx, sX, 0.0, G, ldg,
+                                         sG, batch);
+}
+
+void trsm_strip(hipStream_t st, int T, int rows, int n, const double* X, int ldx, long long sX,
+                const double* Linv, int ldl, long long sL, double* Y, long long sY, int batch)
+{
+    if (rows <= 0 || n <= 0 || batch <= 0) return;
+    strip_dispatch<false, true, 2, false>(T, st, rows, n, n, 1.0, X, ldx, sX, Linv, ldl, sL, 0.0, Y,
+                                          ldx, sY, batch);
+}
+
+void gram_product(hipStream_t st, int code, int n, int rows, const double* X, int ldx, long long sX,
+                  double* G, int ldg, long long sG, int batch)
+{
+    if (code >= 4) {
+        gram_strip(st, code, n, rows, X, ldx, sX, G, ldg, sG, batch);
+        return;
+    }
+    if (n <= 0 || batch <= 0) return;
+    gemm_dispatch<true, false, 0, true>(-1 - code, st, n, n, rows, 1.0, X, ldx, sX, X, ldx, sX, 0.0, G,
+                                        ldg, sG, batch);
+}
+
+void trsm_product(hipStream_t st, int code, int rows, int n, const double* X, int ldx, long long sX,
+                  const double* Linv, int ldl, long long sL, double* Y, long long sY, int batch)
+{
+    if (code >= 4) {
+        trsm_strip(st, code, rows, n, X, ldx, sX, Linv, ldl, sL, Y, sY, batch);
+        return;
+    }
+    if (rows <= 0 || n <= 0 || batch <= 0) return;
+    gemm_dispatch<false, true, 2, false>(-1 - code, st, rows, n, n, 1.0, X, ldx, sX, Linv, ldl, sL, 0.0,
+                                         Y, ldx, sY, batch);
+}
+
+void strip_gemm_nn(hipStream_t st, int T, int M, int N, int K, const double* A, int lda,
+                   const double* B, int ldb, double* C, int ldc)
+{
+    strip_dispatch<false, false, 0, false>(T, st, M, N, K, 1.0, A, lda, 0, B, ldb, 0, 0.0, C, ldc, 0, 1);
+}
+
+// G[n + c*ldg] = sum_r X[r][c] X[r][n]: the rhs row F^T Q of an extended Gram matrix.
+__global__ __launch_bounds__(256) void gram_rhs_row_kernel(const double* X, int ldx, long long sX,
+                                                           int rows, int n, double* G, int ldg,
+                                                           long long sG)
+{
+    const long long z = blockIdx.y;
+    const int lane = threadIdx.x & 63;
+    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c >= n) return;
+    const double* xc = X + z * sX + (long long)c * ldx;
+    const double* xf = X + z * sX + (long long)n * ldx;
+    double v = 0.0;
+    for (int r = lane; r < rows; r += 64) v += xc[r] * xf[r];
+    v = wave_sum(v);
+    if (lane == 0) G[z * sG + (long long)c * ldg + n] = v;
+}
+
+void gram_rhs_row(hipStream_t st, const double* X, int ldx, long long sX, int rows, int n, double* G,
+                  int ldg, long long sG, int batch)
+{
+    dim3 grid((n + 3) / 4, batch);
+    hipLaunchKernelGGL(gram_rhs_row_kernel, grid, dim3(256), 0, st, X, ldx, sX, rows, n, G, ldg, sG);
 }
 
 // ---------------------------------------------------------------------------
@@ -688,6 +934,77 @@ void envelope_step(hipStream_t st, double* A, int lda, long long sA, double* Lo,
     if (rows <= 0) return;
     const int nt = (rows + 63) / 64;
     hipLaunchKernelGGL(envelope_step_kernel, dim3(nt * (nt + 1) / 2, batch), dim3(256), 0, st, A, lda,
+                       sA, Lo, ldo, sLo, j, jb, Dinv, sD, r1, rhs, sR);
+}
+
+// Panel of one envelope Cholesky step without the trailing update: for each
+// 64-row tile I of [j + jb, r1), L_I = A_IJ Dinv^T is written to Lo and the
+// forward-substitution update y_I -= L_I y_J is applied.  Used with a
+// separate trailing-update GEMM when many matrices are factored together.
+__global__ __launch_bounds__(256) void envelope_panel_kernel(const double* A, int lda, long long sA,
+                                                             double* Lo, int ldo, long long sLo,
+                                                             int j, int jb, const double* Dinv,
+                                                             long long sD, int r1, double* rhs,
+                                                             long long sR)
+{
+    __shared__ double Dv[64][65];
+    __shared__ double S1[64][65];
+    __shared__ double yj[64];
+    const long long zb = blockIdx.y;
+    A += zb * sA;
+    Lo += zb * sLo;
+    Dinv += zb * sD;
+    if (rhs) rhs += zb * sR;
+    const int I = j + jb + 64 * blockIdx.x;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int lr = lane & 15, lq = lane >> 4;
+    for (int idx = tid; idx < 64 * 64; idx += 256) {
+        const int c = idx >> 6, r = idx & 63;
+        Dv[r][c] = (r < jb && c < jb) ? Dinv[c * 64 + r] : 0.0;
+        S1[r][c] = (I + r < r1 && c < jb) ? A[(long long)(j + c) * lda + I + r] : 0.0;
+    }
+    if (tid < 64) yj[tid] = (rhs && tid < jb) ? rhs[j + tid] : 0.0;
+    __syncthreads();
+    v4d acc[2][2];
+    for (int u = 0; u < 2; ++u)
+        for (int v = 0; v < 2; ++v) acc[u][v] = (v4d){0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < 64; k0 += 4) {
+        const int kk = k0 + lq;
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int v = 0; v < 2; ++v)
+                acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                    S1[wm * 32 + u * 16 + lr][kk], Dv[wn * 32 + v * 16 + lr][kk], acc[u][v], 0, 0, 0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) S1[wm * 32 + u * 16 + 4 * r + lq][wn * 32 + v * 16 + lr] = acc[u][v][r];
+    __syncthreads();
+    for (int idx = tid; idx < 64 * 64; idx += 256) {
+        const int c = idx >> 6, r = idx & 63;
+        if (I + r < r1 && c < jb) Lo[(long long)(j + c) * ldo + I + r] = S1[r][c];
+    }
+    if (rhs && tid < 64 && I + tid < r1) {
+        double a1 = 0.0;
+        for (int c = 0; c < jb; ++c) a1 += S1[tid][c] * yj[c];
+        rhs[I + tid] -= a1;
+    }
+}
+
+void envelope_panel(hipStream_t st, const double* A, int lda, long long sA, double* Lo, int ldo,
+                    long long sLo, int j, int jb, const double* Dinv, long long sD, int r1,
+                    double* rhs, long long sR, int batch)
+{
+    const int rows = r1 - j - jb;
+    if (rows <= 0) return;
+    hipLaunchKernelGGL(envelope_panel_kernel, dim3((rows + 63) / 64, batch), dim3(256), 0, st, A, lda,
                        sA, Lo, ldo, sLo, j, jb, Dinv, sD, r1, rhs, sR);
 }
 

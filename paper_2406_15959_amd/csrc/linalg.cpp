@@ -44,17 +44,28 @@ void blocked_potrf(hipStream_t st, double* A, int lda, long long sA, int Mrows, 
 
 void envelope_potrf(hipStream_t st, double* A, int lda, long long sA, double* Lo, int ldo,
                     long long sLo, int n, const int* rend, double* Dinv, long long sD, DevInfo* info,
-                    int pass, double* dsave, double* rhs, long long sR, int batch)
+                    int pass, double* dsave, double* rhs, long long sR, int batch, bool fused)
 {
     const double tau = 64.0 * n * 0x1p-53;
     if (dsave) save_diag(st, A, lda, sA, n, dsave, n, batch);
     for (int j = 0, p = 0; j < n; j += NB, ++p) {
         const int jb = std::min(NB, n - j);
         double* Dj = Dinv + (long long)p * NB * NB;
+        const int r1 = std::min(n, rend[p]);
         potrf_diag(st, A, lda, sA, j, jb, Dj, sD, nullptr, 0, 0, info, pass, batch, dsave, n, tau, rhs,
                    sR);
-        envelope_step(st, A, lda, sA, Lo, ldo, sLo, j, jb, Dj, sD, std::min(n, rend[p]), rhs, sR,
-                      batch);
+        if (fused) {
+            // one launch: latency-optimal for a few matrices (panel tiles recomputed per pair)
+            envelope_step(st, A, lda, sA, Lo, ldo, sLo, j, jb, Dj, sD, r1, rhs, sR, batch);
+        } else {
+            // panel, then one trailing GEMM: throughput-optimal for many matrices
+            envelope_panel(st, A, lda, sA, Lo, ldo, sLo, j, jb, Dj, sD, r1, rhs, sR, batch);
+            const int Mb = r1 - j - jb;
+            if (Mb > 0)
+                gemm_f64(st, false, true, 0, true, Mb, Mb, jb, -1.0, Lo + (long long)j * ldo + j + jb, ldo,
+                         sLo, Lo + (long long)j * ldo + j + jb, ldo, sLo, 1.0,
+                         A + (long long)(j + jb) * lda + (j + jb), lda, sA, batch);
+        }
     }
 }
 

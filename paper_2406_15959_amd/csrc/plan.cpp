@@ -38,6 +38,9 @@ struct EdgeOwner {
 struct elmddm_plan {
     elmddm_problem p{};
     int B = 1;    // problem instances per solve (same geometry)
+    int gram_code = -2;   // kernel for the Gram products (see gram_product)
+    int trsm_code = -2;   // kernel for the triangular-solve products
+    bool env_fused = true;
     int NT = 0;   // subdomains over all instances, B * N
     int N = 0, n = 0, nx = 0, ny = 0, q2 = 0, mg = 0, mb = 0;
     int maxb = 0, maxk = 0, max_rows = 0;
@@ -565,6 +568,9 @@ elmddm_status elmddm_plan_create_batch(const elmddm_problem* problem, int32_t ba
     if (!P) return fail(ELMDDM_OOM, "host allocation failed");
     P->p = *problem;
     P->B = batch;
+    // one fused launch per envelope step is latency-optimal for few systems;
+    // a separate panel + trailing GEMM wins once several systems share the launches
+    P->env_fused = batch < 4;
     try {
         st = build(P);
     } catch (const std::bad_alloc&) {
@@ -687,16 +693,16 @@ elmddm_status elmddm_solve(elmddm_plan* P, const double* W, const double* b, con
     for (int pass = 1; pass <= 3; ++pass) {
         const int ncol = pass == 3 ? n + 1 : n;
         if (P->timing) (void)hipEventRecord(P->pev[3 * (pass - 1)], st);
-        gemm_f64(st, true, false, 0, true, ncol, ncol, P->gram_rows, 1.0, src, ldx, P->sX, src, ldx,
-                 P->sX, 0.0, P->G, ldg, P->sG, N);
+        gram_product(st, P->gram_code, n, P->gram_rows, src, ldx, P->sX, P->G, ldg, P->sG, N);
+        if (pass == 3) gram_rhs_row(st, src, ldx, P->sX, P->gram_rows, n, P->G, ldg, P->sG, N);
         if (P->timing) (void)hipEventRecord(P->pev[3 * (pass - 1) + 1], st);
         if (pass == 1) scale_diag(st, P->G, ldg, P->sG, n, 1.0 + shift, N);
         blocked_potrf(st, P->G, ldg, P->sG, ncol, n, P->Dinv, P->sD, P->Linv[pass - 1], ldg, P->sL,
                       P->Tbuf, P->d_info, pass, N, P->dsave, n);
         if (P->timing) (void)hipEventRecord(P->pev[3 * (pass - 1) + 2], st);
         const int r0 = pass == 3 ? P->mI : 0;
-        gemm_f64(st, false, true, 2, false, ldx - r0, n, n, 1.0, src + r0, ldx, P->sX,
-                 P->Linv[pass - 1], ldg, P->sL, 0.0, dst + r0, ldx, P->sX, N);
+        trsm_product(st, P->trsm_code, ldx - r0, n, src + r0, ldx, P->sX, P->Linv[pass - 1], ldg, P->sL,
+                     dst + r0, P->sX, N);
         if (pass < 3) std::swap(src, dst);
     }
     if (P->timing) (void)hipEventRecord(P->pev[9], st);
@@ -731,7 +737,7 @@ elmddm_status elmddm_solve(elmddm_plan* P, const double* W, const double* b, con
         // block by block, then back to the interface numbering.
         const long long sDS = (long long)P->nblkS * NB * NB;
         envelope_potrf(st, P->Sx, P->lds, sS, P->SL, P->lds, sS, P->nG, P->rend.data(), P->DinvS, sDS,
-                       P->d_info, 4, P->dsave, P->yvec, P->nG, B);
+                       P->d_info, 4, P->dsave, P->yvec, P->nG, B, P->env_fused);
         P->mark(6, st);
         const int BR = 4 * NB;
         for (int j0 = (P->nG - 1) / BR * BR; j0 >= 0; j0 -= BR) {
@@ -755,6 +761,55 @@ elmddm_status elmddm_solve(elmddm_plan* P, const double* W, const double* b, con
     if (P->nG > 0) check_finite(st, u_gamma, (long long)B * P->nG, P->d_info);
     if (P->timing) P->ev_pending = true;
     return check_launch("back-solve");
+}
+
+elmddm_status elmddm_autotune(elmddm_plan* P, void* stream, int32_t* choice)
+{
+    if (!P) return fail(ELMDDM_INVALID_ARG, "NULL plan");
+    hipStream_t st = (hipStream_t)stream;
+    const int N = P->NT, n = P->n, ldx = P->ldx, ldg = P->ldg;
+    // timing only: operand values do not matter, but must be finite
+    if (hipMemsetAsync(P->X0, 0, (size_t)N * P->sX * sizeof(double), st) != hipSuccess)
+        return check_launch("autotune memset");
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return check_launch("autotune events");
+    const int codes[] = {-1, -2, -3, -4, 4, 5, 6, 7, 8};
+    auto time_it = [&](auto&& fn) {
+        fn();
+        (void)hipEventRecord(e0, st);
+        fn();
+        fn();
+        (void)hipEventRecord(e1, st);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        return ms;
+    };
+    float best_g = 1e30f, best_t = 1e30f;
+    for (int code : codes) {
+        const float tg = time_it([&] {
+            gram_product(st, code, n, P->gram_rows, P->X0, ldx, P->sX, P->G, ldg, P->sG, N);
+        });
+        if (tg < best_g) {
+            best_g = tg;
+            P->gram_code = code;
+        }
+        const float tt = time_it([&] {
+            trsm_product(st, code, ldx, n, P->X0, ldx, P->sX, P->Linv[0], ldg, P->sL, P->X1, P->sX, N);
+        });
+        if (tt < best_t) {
+            best_t = tt;
+            P->trsm_code = code;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (choice) {
+        choice[0] = P->gram_code;
+        choice[1] = P->trsm_code;
+    }
+    return check_launch("autotune");
 }
 
 elmddm_status elmddm_solve_info(elmddm_plan* P, elmddm_info* info)

@@ -38,6 +38,30 @@ int elmddm_test_gemm(int ta, int tb, int kmode, int lower, int M, int N, int K, 
 
 void elmddm_test_set_gemm_variant(int which, int v) { set_gemm_variant(which, v); }
 
+int elmddm_test_strip_width(int n) { return strip_width(n); }
+
+// Plain column-major C = A B with the strip kernel of width T (4..8).
+int elmddm_test_strip_gemm(int T, int M, int N, int K, const double* A, int lda, const double* B,
+                           int ldb, double* C, int ldc, void* stream)
+{
+    strip_gemm_nn((hipStream_t)stream, T, M, N, K, A, lda, B, ldb, C, ldc);
+    return hipGetLastError() == hipSuccess ? 0 : 7;
+}
+
+int elmddm_test_gram_strip(int n, int rows, const double* X, int ldx, long long sX, double* G, int ldg,
+                           long long sG, int batch, void* stream)
+{
+    gram_strip((hipStream_t)stream, strip_width(n), n, rows, X, ldx, sX, G, ldg, sG, batch);
+    return hipGetLastError() == hipSuccess ? 0 : 7;
+}
+
+int elmddm_test_trsm_strip(int rows, int n, const double* X, int ldx, long long sX, const double* Li,
+                           int ldl, long long sL, double* Y, long long sY, int batch, void* stream)
+{
+    trsm_strip((hipStream_t)stream, strip_width(n), rows, n, X, ldx, sX, Li, ldl, sL, Y, sY, batch);
+    return hipGetLastError() == hipSuccess ? 0 : 7;
+}
+
 // info: device int32[4] (status, bad_subdomain, bad_pass, pad), initialised by the caller.
 int elmddm_test_potrf(double* A, int lda, long long sA, int Mrows, int n, double* Dinv,
                       long long sD, double* Linv, int ldl, long long sL, double* Tbuf, int* info,

@@ -21,6 +21,8 @@ def hooks(gpu):
     L.elmddm_test_gemm.argtypes = [i32, i32, i32, i32, i32, i32, i32, d, vp, i32, i64, vp, i32, i64,
                                    d, vp, i32, i64, i32, vp]
     L.elmddm_test_mfma_layout.argtypes = [vp, vp, vp, vp]
+    L.elmddm_test_gram_strip.argtypes = [i32, i32, vp, i32, i64, vp, i32, i64, i32, vp]
+    L.elmddm_test_trsm_strip.argtypes = [i32, i32, vp, i32, i64, vp, i32, i64, vp, i64, i32, vp]
     L.elmddm_test_potrf.argtypes = [vp, i32, i64, i32, i32, vp, i64, vp, i32, i64, vp, vp, i32, vp]
     return L
 
@@ -174,3 +176,46 @@ def test_cholesky_reports_indefinite_matrix(hooks):
     assert st == 0
     torch.cuda.synchronize()
     assert info[0].item() == 3 and info[1].item() == 0
+
+
+@pytest.mark.parametrize("n,rows,batch", [(400, 1856, 2), (100, 480, 3), (30, 70, 2), (200, 900, 1), (1000, 300, 1)])
+def test_gram_strip_lower_triangle(hooks, n, rows, batch):
+    import torch
+    assert 4 <= hooks.elmddm_test_strip_width(n) <= 8
+    rng = np.random.default_rng(n + rows)
+    ldx, ldg = rows + 8, n + 5
+    X = rng.standard_normal((batch, n + 1, ldx))      # [col][row]
+    dX = _dev(X)
+    dG = torch.zeros(batch * (n + 1) * ldg, dtype=torch.float64, device="cuda:0")
+    st = hooks.elmddm_test_gram_strip(n, rows, _p(dX), ldx, (n + 1) * ldx, _p(dG), ldg, (n + 1) * ldg, batch, _stream())
+    assert st == 0
+    torch.cuda.synchronize()
+    G = dG.cpu().numpy().reshape(batch, n + 1, ldg)
+    for z in range(batch):
+        Xz = X[z, :n, :rows].T
+        ref = Xz.T @ Xz
+        got = G[z, :n, :n].T                         # back to row-major math orientation
+        mask = np.tril(np.ones((n, n), bool))
+        assert np.abs(np.where(mask, got - ref, 0)).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("rows,n,batch", [(2016, 400, 2), (480, 100, 3), (70, 30, 2), (333, 200, 1)])
+def test_trsm_strip_matches_product_with_triangular_inverse(hooks, rows, n, batch):
+    import torch
+    rng = np.random.default_rng(rows + n)
+    ldx, ldl = rows + 4, n + 3
+    X = rng.standard_normal((batch, n + 1, ldx))
+    Li = np.zeros((batch, n, ldl))
+    for z in range(batch):
+        Li[z, :, :n] = np.tril(rng.standard_normal((n, n))).T    # col-major lower
+    dX, dL = _dev(X), _dev(Li)
+    dY = torch.zeros_like(dX)
+    st = hooks.elmddm_test_trsm_strip(rows, n, _p(dX), ldx, (n + 1) * ldx, _p(dL), ldl, n * ldl, _p(dY), (n + 1) * ldx, batch, _stream())
+    assert st == 0
+    torch.cuda.synchronize()
+    Y = dY.cpu().numpy()
+    for z in range(batch):
+        Lz = Li[z, :, :n].T
+        ref = X[z, :n, :rows].T @ Lz.T
+        got = Y[z, :n, :rows].T
+        assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()

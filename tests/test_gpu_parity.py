@@ -207,3 +207,32 @@ def test_batched_failure_names_the_instance(gpu):
     info = plan.solve_info()
     assert info.status == B.NOT_SPD
     assert (info.bad_instance, info.bad_subdomain) == (1, 3)
+
+
+def test_autotuned_kernels_and_split_envelope_path_match_oracle(gpu):
+    """Batch 4 takes the split (panel + trailing GEMM) envelope path; the
+    autotuner may pick any of the product kernels; parity must hold."""
+    import torch
+    from oracle import ddm
+    from oracle.layout import build_layout
+    from paper_2406_15959_amd import binding as B
+    P = wl.Problem(4, 3, 130, 13, 12, 12, 17, R=2.5)
+    nb = 4
+    plan = B.Plan(to_c_problem(P), batch=nb)
+    codes = plan.autotune()
+    assert len(codes) == 2 and all(c < 0 or 4 <= c <= 8 for c in codes)
+    s = plan.sizes
+    f, g, _ = wl.sample_data(P, plan.points(B.POINTS_INTERIOR), plan.points(B.POINTS_BOUNDARY))
+    seeds = [41, 42, 43, 44]
+    Ws, bs = zip(*[wl.hidden_params(P, sd) for sd in seeds])
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    du = torch.zeros(nb * s.n_interface, dtype=torch.float64, device="cuda")
+    dc = torch.zeros(nb * s.nsub * s.neurons, dtype=torch.float64, device="cuda")
+    plan.solve(t(np.stack(Ws)), t(np.stack(bs)), t(np.stack([f] * nb)), t(np.stack([g] * nb)), None, du, dc)
+    assert plan.solve_info().status == 0
+    U = du.cpu().numpy().reshape(nb, -1)
+    lay = build_layout(P)
+    data = ddm.problem_data(P, lay, wl.source_f, wl.boundary_g, wl.coefficient)
+    for i in (0, 3):
+        o = ddm.solve(P, Ws[i], bs[i], data, lay)
+        assert rel(U[i], o.u_gamma) <= TOL_FP64
