@@ -27,6 +27,26 @@ sys.path.insert(0, ROOT)
 
 MFMA_F64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
 HBM_PEAK_GBS = 8000.0
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "gram_8x8_fp64_batch8_pmc.txt")
+
+
+def measured_traffic(gram_code, batch):
+    """HBM bytes per Gram launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary, if it was taken with this kernel source, kernel choice and batch; else None."""
+    import hashlib
+    try:
+        kv = {}
+        for line in open(PMC_SUMMARY):
+            if ":" in line:
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        src = os.path.join(ROOT, "paper_2406_15959_amd", "csrc", "kernels.hip")
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if kv.get("kernels_hip_sha256") != sha or int(kv["gram_code"]) != gram_code or int(kv["batch"]) != batch:
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def main():
@@ -36,7 +56,19 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=8, help="problem instances solved together per step")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (counter calibration) and exit")
     args = ap.parse_args()
+    if args.calibrate_copy_mib > 0:
+        import torch
+        nbytes = args.calibrate_copy_mib << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_dispatch": nbytes, "dispatches": 3}), flush=True)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
@@ -132,17 +164,17 @@ def main():
 
     # Roofline of the dominant kernel: the batched FP64 MFMA Gram (SYRK)
     # launch.  Algorithmic work per launch: sum over subdomains of
-    # m_s * n * (n + 1) flops (symmetric product, lower triangle); the third
-    # CholeskyQR pass adds the right-hand-side row, 2 m_s n flops.
+    # m_s * n * (n + 1) flops (symmetric product, lower triangle).
     m_rows = P.q_x * P.q_y + 4 * P.m_ifc_edge if P.m_ifc_edge == P.m_bdry_edge else s.max_rows
     n = P.neurons
-    flops_per_solve = P.nsub * m_rows * (3 * n * (n + 1) + 2 * n)
-    gram_ms = stage_ms[1] / max(nsolved, 1) / 3.0
+    flops_per_solve = P.nsub * m_rows * 3 * n * (n + 1)
+    gram_ms = stage_ms[1] / max(nsolved, 1) / 3.0          # average Gram launch (HIP events)
     achieved = nb * flops_per_solve / 3.0 / (gram_ms * 1e-3) / 1e12 if gram_ms > 0 else 0.0
     kname = ("gemm_strip_kernel<T=%d>" % tuned[0]) if tuned[0] >= 4 else ("gemm_f64_kernel variant %d" % (-1 - tuned[0]))
     roofline = {"bound": "mfma", "kernel": "gram product, " + kname,
                 "achieved": achieved, "peak": MFMA_F64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / MFMA_F64_PEAK_TFLOPS, "traffic": None,
+                "frac": achieved / MFMA_F64_PEAK_TFLOPS, "traffic": measured_traffic(tuned[0], nb),
+                "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "avg_launch_ms": gram_ms}
     stages = {name: v / max(nsolved, 1) for name, v in zip(B.STAGE_NAMES, stage_ms)}   # per step
     ok = parity.get("ok", info.status == 0)

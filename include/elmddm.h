@@ -195,7 +195,7 @@ elmddm_status elmddm_autotune(elmddm_plan* plan, void* stream, int32_t* choice);
  * elapsed time of each stage to running totals; elmddm_stage_times
  * synchronises the last solve's stream and reads the totals (milliseconds)
  * and the number of solves they cover.  Stages:
- *   0 feature assembly            1 Gram matrices (3 MFMA SYRK launches)
+ *   0 feature assembly            1 Gram products (exactly the 3 MFMA Gram launches)
  *   2 local Cholesky + inverses   3 triangular solves (3 MFMA GEMM launches)
  *   4 Schur complement assembly   5 interface Cholesky
  *   6 interface back-substitution 7 local back-solve

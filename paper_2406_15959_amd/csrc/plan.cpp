@@ -694,8 +694,8 @@ elmddm_status elmddm_solve(elmddm_plan* P, const double* W, const double* b, con
         const int ncol = pass == 3 ? n + 1 : n;
         if (P->timing) (void)hipEventRecord(P->pev[3 * (pass - 1)], st);
         gram_product(st, P->gram_code, n, P->gram_rows, src, ldx, P->sX, P->G, ldg, P->sG, N);
-        if (pass == 3) gram_rhs_row(st, src, ldx, P->sX, P->gram_rows, n, P->G, ldg, P->sG, N);
         if (P->timing) (void)hipEventRecord(P->pev[3 * (pass - 1) + 1], st);
+        if (pass == 3) gram_rhs_row(st, src, ldx, P->sX, P->gram_rows, n, P->G, ldg, P->sG, N);
         if (pass == 1) scale_diag(st, P->G, ldg, P->sG, n, 1.0 + shift, N);
         blocked_potrf(st, P->G, ldg, P->sG, ncol, n, P->Dinv, P->sD, P->Linv[pass - 1], ldg, P->sL,
                       P->Tbuf, P->d_info, pass, N, P->dsave, n);
