@@ -68,6 +68,9 @@ typedef enum elmddm_status {
 
 enum { ELMDDM_OP_POISSON = 0, ELMDDM_OP_VARCOEF = 1 };
 
+/* Precision modes (see elmddm_plan_set_mode). */
+enum { ELMDDM_MODE_FP64 = 0, ELMDDM_MODE_MIXED = 1 };
+
 enum {
     ELMDDM_POINTS_INTERIOR = 0,   /* nsub * q_x * q_y points, box-major          */
     ELMDDM_POINTS_BOUNDARY = 1,   /* all Dirichlet points, box-major, local order */
@@ -179,6 +182,22 @@ elmddm_status elmddm_assemble(elmddm_plan* plan, const double* W, const double* 
 elmddm_status elmddm_plan_keep_schur(elmddm_plan* plan, int32_t keep);
 elmddm_status elmddm_get_schur(elmddm_plan* plan, double* S, double* rhs, void* stream);
 
+/* Precision mode of later solves on this plan.
+ *  ELMDDM_MODE_FP64 (default): every product in float64.
+ *  ELMDDM_MODE_MIXED: the Gram matrices of the first CholeskyQR pass are
+ *    formed on the matrix cores from float32-rounded features with float32
+ *    accumulation, and that pass's diagonal shift is raised from the float64
+ *    bound to s = 16 sqrt(m n) u32 (u32 = 2^-24) times diag(G) so that it
+ *    covers the float32 rounding of the Gram entries.  The first pass only
+ *    conditions the features (its factor is used as a triangular right
+ *    preconditioner, applied in float64); passes 2 and 3, the Cholesky
+ *    factorisations, the Schur complement and the interface solve stay
+ *    float64, so the result agrees with the float64 mode to float64
+ *    accuracy whenever the shifted pass leaves the preconditioned features
+ *    with condition number below about 1e7.
+ * Returns INVALID_ARG for an unknown mode. */
+elmddm_status elmddm_plan_set_mode(elmddm_plan* plan, int32_t mode);
+
 /* Time the candidate kernels for the two large local products (the Gram
  * matrices of the CholeskyQR passes and the triangular solves) on this plan's
  * shapes and keep the fastest for later solves: the 64 x 64 tile kernel in
@@ -203,6 +222,12 @@ elmddm_status elmddm_autotune(elmddm_plan* plan, void* stream, int32_t* choice);
 #define ELMDDM_NUM_STAGES 8
 elmddm_status elmddm_set_timing(elmddm_plan* plan, int32_t enable);
 elmddm_status elmddm_stage_times(elmddm_plan* plan, double* ms, int32_t* solves);
+
+/* The local-factorisation stages split by CholeskyQR pass (same timing
+ * switch and totals as elmddm_stage_times): ms[3 p + 0] Gram product,
+ * ms[3 p + 1] Cholesky + inverses, ms[3 p + 2] triangular solve of pass
+ * p + 1 (p = 0, 1, 2), in milliseconds summed over the timed solves. */
+elmddm_status elmddm_pass_times(elmddm_plan* plan, double* ms, int32_t* solves);
 
 const char* elmddm_status_string(elmddm_status status);
 const char* elmddm_last_error(void);

@@ -28,12 +28,14 @@ OP_VARCOEF = 1
 POINTS_INTERIOR = 0
 POINTS_BOUNDARY = 1
 POINTS_INTERFACE = 2
+MODE_FP64 = 0
+MODE_MIXED = 1
 
 EXPORTED = [
     "elmddm_plan_create", "elmddm_plan_create_batch", "elmddm_plan_destroy", "elmddm_plan_sizes", "elmddm_points",
     "elmddm_solve", "elmddm_solve_info", "elmddm_eval", "elmddm_assemble",
-    "elmddm_plan_keep_schur", "elmddm_get_schur", "elmddm_set_timing", "elmddm_stage_times",
-    "elmddm_autotune",
+    "elmddm_plan_keep_schur", "elmddm_get_schur", "elmddm_set_timing", "elmddm_stage_times", "elmddm_pass_times",
+    "elmddm_autotune", "elmddm_plan_set_mode",
     "elmddm_status_string", "elmddm_last_error",
 ]
 
@@ -91,7 +93,9 @@ def lib():
         L.elmddm_get_schur.argtypes = [vp, dp, dp, vp]
         L.elmddm_set_timing.argtypes = [vp, i32]
         L.elmddm_autotune.argtypes = [vp, vp, ctypes.POINTER(i32)]
+        L.elmddm_plan_set_mode.argtypes = [vp, i32]
         L.elmddm_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]
+        L.elmddm_pass_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]
         L.elmddm_status_string.argtypes = [i32]
         L.elmddm_status_string.restype = ctypes.c_char_p
         L.elmddm_last_error.restype = ctypes.c_char_p
@@ -175,6 +179,10 @@ class Plan:
         _check(lib().elmddm_assemble(self._h, _ptr(W), _ptr(b), _ptr(f), _ptr(g), _ptr(coef),
                                      _ptr(K), _ptr(A), _ptr(F), _stream()))
 
+    def set_mode(self, mode):
+        """MODE_FP64 or MODE_MIXED for later solves."""
+        _check(lib().elmddm_plan_set_mode(self._h, mode))
+
     def keep_schur(self, keep=True):
         _check(lib().elmddm_plan_keep_schur(self._h, 1 if keep else 0))
 
@@ -193,6 +201,13 @@ class Plan:
         n = ctypes.c_int32()
         _check(lib().elmddm_stage_times(self._h, ms, ctypes.byref(n)))
         return list(ms), n.value
+
+    def pass_times(self):
+        """([[gram, cholesky, trsm] ms for passes 1..3] summed over timed solves, number of solves)."""
+        ms = (ctypes.c_double * 9)()
+        n = ctypes.c_int32()
+        _check(lib().elmddm_pass_times(self._h, ms, ctypes.byref(n)))
+        return [list(ms[3 * p:3 * p + 3]) for p in range(3)], n.value
 
     def get_schur(self, S, rhs):
         _check(lib().elmddm_get_schur(self._h, _ptr(S), _ptr(rhs), _stream()))

@@ -62,6 +62,10 @@ void gram_product(hipStream_t st, int code, int n, int rows, const double* X, in
 void trsm_product(hipStream_t st, int code, int rows, int n, const double* X, int ldx, long long sX,
                   const double* Linv, int ldl, long long sL, double* Y, long long sY, int batch);
 // G = X^T X (lower triangle) over `rows` rows and n columns of every X in the batch.
+// Gram product in FP32 (operands rounded to FP32, FP32 accumulation on the
+// matrix cores), lower triangle written as FP64.
+void gram_product_f32(hipStream_t st, int n, int rows, const double* X, int ldx, long long sX,
+                      double* G, int ldg, long long sG, int batch);
 void gram_strip(hipStream_t st, int T, int n, int rows, const double* X, int ldx, long long sX,
                 double* G, int ldg, long long sG, int batch);
 // Y = X Linv^T for Linv lower triangular (n x n); X, Y: rows x n, leading dimension ldx.

@@ -108,7 +108,8 @@ void assemble(hipStream_t st, int N, int ngeo, long long nbnd, int ldx, int n, c
 }
 
 // ---------------------------------------------------------------------------
-// Batched FP64 GEMM on the matrix cores: C = alpha op(A) op(B) + beta C.
+// Batched GEMM on the matrix cores: C = alpha op(A) op(B) + beta C, FP64
+// operands and result, computed in FP64 (or, for the mixed-precision Gram, FP32).
 // Workgroup tile 64x64, K staged 32 at a time through LDS, four waves in a
 // 2x2 arrangement, each wave a 32x32 block of 2x2 V_MFMA_F64_16X16X4 tiles.
 // MFMA operand layout (16x16x4, f64): lane l holds A[l%16][l/16] and
@@ -128,11 +129,19 @@ __device__ __forceinline__ bool aligned16(const double* p)
     return (reinterpret_cast<uintptr_t>(p) & 15u) == 0;
 }
 
-template <bool TA, bool TB, int KMODE, bool LOWER, int GB_K, bool XCD>
-__global__ __launch_bounds__(256) void gemm_f64_kernel(
+// Compute type CT: double (V_MFMA_F64_16X16X4) or float (V_MFMA_F32_16X16X4,
+// FP32 accumulation; operands rounded to FP32 when they are staged in LDS,
+// result widened to FP64 on store).  The FP32 accumulator's element r of lane
+// l is D[4*(l/16) + r][l%16].  LDS rows are padded so that the four k rows a
+// wave reads at once fall in different banks.
+template <class CT, bool TA, bool TB, int KMODE, bool LOWER, int GB_K, bool XCD>
+__global__ __launch_bounds__(256) void gemm_mfma_kernel(
     int M, int N, int K, double alpha, const double* A, int lda, long long sA, const double* B,
     int ldb, long long sB, double beta, double* C, int ldc, long long sC)
 {
+    constexpr bool F64 = sizeof(CT) == 8;
+    constexpr int PAD = F64 ? 0 : 16;
+    typedef CT acc_t __attribute__((ext_vector_type(4)));
     const unsigned gx = gridDim.x, gy = gridDim.y;
     const unsigned total = gx * gy * gridDim.z;
     const unsigned p = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
@@ -148,16 +157,16 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(
     if (KMODE == 1) kbeg = n0 < K ? n0 : K;
     if (KMODE == 2) kend = (n0 + GB_N) < K ? (n0 + GB_N) : K;
 
-    __shared__ double As[GB_K][GB_M];
-    __shared__ double Bs[GB_K][GB_N];
+    __shared__ CT As[GB_K][GB_M + PAD];
+    __shared__ CT Bs[GB_K][GB_N + PAD];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1;
 
-    v4d acc[2][2];
+    acc_t acc[2][2];
     for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < 2; ++j) acc[i][j] = (acc_t){0, 0, 0, 0};
 
     // Per thread and stage: V = GB_K / 4 consecutive doubles of A and of B.
     // "along-row": k = tid / (64 / V), V consecutive m (or n) from (tid % (64/V)) * V.
@@ -203,20 +212,20 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(
         if (!TA) {
             const int k = tid / RS, m = (tid % RS) * V;
 #pragma unroll
-            for (int e = 0; e < V; ++e) As[k][m + e] = ra[e];
+            for (int e = 0; e < V; ++e) As[k][m + e] = (CT)ra[e];
         } else {
             const int m = tid >> 2, k = (tid & 3) * V;
 #pragma unroll
-            for (int e = 0; e < V; ++e) As[k + e][m] = ra[e];
+            for (int e = 0; e < V; ++e) As[k + e][m] = (CT)ra[e];
         }
         if (!TB) {
             const int nn = tid >> 2, k = (tid & 3) * V;
 #pragma unroll
-            for (int e = 0; e < V; ++e) Bs[k + e][nn] = rb[e];
+            for (int e = 0; e < V; ++e) Bs[k + e][nn] = (CT)rb[e];
         } else {
             const int k = tid / RS, nn = (tid % RS) * V;
 #pragma unroll
-            for (int e = 0; e < V; ++e) Bs[k][nn + e] = rb[e];
+            for (int e = 0; e < V; ++e) Bs[k][nn + e] = (CT)rb[e];
         }
     };
 
@@ -228,7 +237,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(
         const int lr = lane & 15, lk = lane >> 4;
         for (int it = 0; it < nk; ++it) {
             if (it + 1 < nk) load(kbeg + (it + 1) * GB_K);
-            double av[GB_K / 4][2], bv[GB_K / 4][2];
+            CT av[GB_K / 4][2], bv[GB_K / 4][2];
 #pragma unroll
             for (int ks = 0; ks < GB_K / 4; ++ks) {
                 const int k = ks * 4 + lk;
@@ -243,7 +252,10 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(
                 for (int u = 0; u < 2; ++u)
 #pragma unroll
                     for (int v = 0; v < 2; ++v)
-                        acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks][u], bv[ks][v], acc[u][v], 0, 0, 0);
+                        if constexpr (F64)
+                            acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks][u], bv[ks][v], acc[u][v], 0, 0, 0);
+                        else
+                            acc[u][v] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ks][u], bv[ks][v], acc[u][v], 0, 0, 0);
             __syncthreads();
             if (it + 1 < nk) {
                 store();
@@ -258,11 +270,11 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(
         for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = m0 + wm * 32 + bi * 16 + r * 4 + lq;
+                const int row = m0 + wm * 32 + bi * 16 + (F64 ? r * 4 + lq : lq * 4 + r);
                 const int col = n0 + wn * 32 + bj * 16 + lr;
                 if (row < M && col < N) {
                     const long long ci = (long long)col * ldc + row;
-                    double v = alpha * acc[bi][bj][r];
+                    double v = alpha * (double)acc[bi][bj][r];
                     if (beta != 0.0) v += beta * C[ci];
                     C[ci] = v;
                 }
@@ -278,13 +290,13 @@ void set_gemm_variant(int which, int v)
     if (which >= 0 && which < 2 && v >= 0 && v < 4) g_gemm_variant[which] = v;
 }
 
-template <bool TA, bool TB, int KMODE, bool LOWER, int BK, bool XCD>
+template <bool TA, bool TB, int KMODE, bool LOWER, int BK, bool XCD, class CT = double>
 static void gemm_launch(hipStream_t st, int M, int N, int K, double alpha, const double* A, int lda,
                         long long sA, const double* B, int ldb, long long sB, double beta,
                         double* C, int ldc, long long sC, int batch)
 {
     dim3 grid((M + GB_M - 1) / GB_M, (N + GB_N - 1) / GB_N, batch);
-    hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, KMODE, LOWER, BK, XCD>), grid, dim3(256), 0, st, M,
+    hipLaunchKernelGGL((gemm_mfma_kernel<CT, TA, TB, KMODE, LOWER, BK, XCD>), grid, dim3(256), 0, st, M,
                        N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
 }
 
@@ -523,6 +535,16 @@ void gram_product(hipStream_t st, int code, int n, int rows, const double* X, in
     if (n <= 0 || batch <= 0) return;
     gemm_dispatch<true, false, 0, true>(-1 - code, st, n, n, rows, 1.0, X, ldx, sX, X, ldx, sX, 0.0, G,
                                         ldg, sG, batch);
+}
+
+// Gram product with FP32 operands and FP32 accumulation (lower triangle,
+// widened to FP64): the first, shifted pass of the mixed-precision mode.
+void gram_product_f32(hipStream_t st, int n, int rows, const double* X, int ldx, long long sX,
+                      double* G, int ldg, long long sG, int batch)
+{
+    if (n <= 0 || batch <= 0) return;
+    gemm_launch<true, false, 0, true, 32, true, float>(st, n, n, rows, 1.0, X, ldx, sX, X, ldx, sX, 0.0,
+                                                       G, ldg, sG, batch);
 }
 
 void trsm_product(hipStream_t st, int code, int rows, int n, const double* X, int ldx, long long sX,

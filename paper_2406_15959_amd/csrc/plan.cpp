@@ -41,6 +41,7 @@ struct elmddm_plan {
     int gram_code = -2;   // kernel for the Gram products (see gram_product)
     int trsm_code = -2;   // kernel for the triangular-solve products
     bool env_fused = true;
+    int mode = ELMDDM_MODE_FP64;
     int NT = 0;   // subdomains over all instances, B * N
     int N = 0, n = 0, nx = 0, ny = 0, q2 = 0, mg = 0, mb = 0;
     int maxb = 0, maxk = 0, max_rows = 0;
@@ -83,6 +84,7 @@ struct elmddm_plan {
     bool ev_ready = false;
     bool ev_pending = false;
     double stage_ms[ELMDDM_NUM_STAGES] = {};
+    double pass_ms[9] = {};   // per CholeskyQR pass: Gram, Cholesky + inverses, triangular solve
     int timed_solves = 0;
 
     template <class T>
@@ -127,9 +129,15 @@ struct elmddm_plan {
         };
         stage_ms[0] += el(ev[0], ev[1]);
         for (int p = 0; p < 3; ++p) {
-            stage_ms[1] += el(pev[3 * p], pev[3 * p + 1]);
-            stage_ms[2] += el(pev[3 * p + 1], pev[3 * p + 2]);
-            stage_ms[3] += el(pev[3 * p + 2], p < 2 ? pev[3 * p + 3] : pev[9]);
+            const double tg = el(pev[3 * p], pev[3 * p + 1]);
+            const double tc = el(pev[3 * p + 1], pev[3 * p + 2]);
+            const double tt = el(pev[3 * p + 2], p < 2 ? pev[3 * p + 3] : pev[9]);
+            stage_ms[1] += tg;
+            stage_ms[2] += tc;
+            stage_ms[3] += tt;
+            pass_ms[3 * p] += tg;
+            pass_ms[3 * p + 1] += tc;
+            pass_ms[3 * p + 2] += tt;
         }
         stage_ms[3] += el(pev[9], ev[4]);
         for (int i = 4; i < ELMDDM_NUM_STAGES; ++i) stage_ms[i] += el(ev[i], ev[i + 1]);
@@ -645,6 +653,14 @@ elmddm_status elmddm_plan_keep_schur(elmddm_plan* P, int32_t keep)
     return ELMDDM_OK;
 }
 
+elmddm_status elmddm_plan_set_mode(elmddm_plan* P, int32_t mode)
+{
+    if (!P) return fail(ELMDDM_INVALID_ARG, "NULL plan");
+    if (mode != ELMDDM_MODE_FP64 && mode != ELMDDM_MODE_MIXED) return fail(ELMDDM_INVALID_ARG, "unknown precision mode");
+    P->mode = mode;
+    return ELMDDM_OK;
+}
+
 elmddm_status elmddm_get_schur(elmddm_plan* P, double* S, double* rhs, void* stream)
 {
     if (!P || !S || !rhs) return fail(ELMDDM_INVALID_ARG, "NULL argument");
@@ -687,13 +703,21 @@ elmddm_status elmddm_solve(elmddm_plan* P, const double* W, const double* b, con
     // diagonal by s * diag(G) (column-scaled shift), pass 3 also factors the
     // extra row F^T Q2, which becomes h = Q^T F.
     const double u = 0x1p-53;
-    const double shift = 11.0 * ((double)P->gram_rows * n + (double)n * (n + 1)) * u * n;
+    const bool mixed = P->mode == ELMDDM_MODE_MIXED;
+    // FP64: the bound of Fukaya et al. for column-scaled X; mixed: a shift that
+    // covers the FP32 rounding of the pass-1 Gram entries (errors of order
+    // sqrt(m) u32 relative to |k_i||k_j|, spectral norm a few sqrt(n) times that).
+    const double shift = mixed ? 16.0 * std::sqrt((double)P->gram_rows * n) * 0x1p-24
+                               : 11.0 * ((double)P->gram_rows * n + (double)n * (n + 1)) * u * n;
     double* src = P->X0;
     double* dst = P->X1;
     for (int pass = 1; pass <= 3; ++pass) {
         const int ncol = pass == 3 ? n + 1 : n;
         if (P->timing) (void)hipEventRecord(P->pev[3 * (pass - 1)], st);
-        gram_product(st, P->gram_code, n, P->gram_rows, src, ldx, P->sX, P->G, ldg, P->sG, N);
+        if (pass == 1 && mixed)
+            gram_product_f32(st, n, P->gram_rows, src, ldx, P->sX, P->G, ldg, P->sG, N);
+        else
+            gram_product(st, P->gram_code, n, P->gram_rows, src, ldx, P->sX, P->G, ldg, P->sG, N);
         if (P->timing) (void)hipEventRecord(P->pev[3 * (pass - 1) + 1], st);
         if (pass == 3) gram_rhs_row(st, src, ldx, P->sX, P->gram_rows, n, P->G, ldg, P->sG, N);
         if (pass == 1) scale_diag(st, P->G, ldg, P->sG, n, 1.0 + shift, N);
@@ -851,6 +875,7 @@ elmddm_status elmddm_set_timing(elmddm_plan* P, int32_t enable)
     P->ev_pending = false;
     P->timing = enable != 0;
     for (double& v : P->stage_ms) v = 0.0;
+    for (double& v : P->pass_ms) v = 0.0;
     P->timed_solves = 0;
     return ELMDDM_OK;
 }
@@ -860,6 +885,15 @@ elmddm_status elmddm_stage_times(elmddm_plan* P, double* ms, int32_t* solves)
     if (!P || !ms) return fail(ELMDDM_INVALID_ARG, "NULL argument");
     P->harvest();
     for (int i = 0; i < ELMDDM_NUM_STAGES; ++i) ms[i] = P->stage_ms[i];
+    if (solves) *solves = P->timed_solves;
+    return ELMDDM_OK;
+}
+
+elmddm_status elmddm_pass_times(elmddm_plan* P, double* ms, int32_t* solves)
+{
+    if (!P || !ms) return fail(ELMDDM_INVALID_ARG, "NULL argument");
+    P->harvest();
+    for (int i = 0; i < 9; ++i) ms[i] = P->pass_ms[i];
     if (solves) *solves = P->timed_solves;
     return ELMDDM_OK;
 }

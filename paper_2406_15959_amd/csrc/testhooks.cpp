@@ -18,7 +18,33 @@ __global__ void mfma_probe_kernel(const double* a, const double* b, double* out)
     for (int r = 0; r < 4; ++r) out[l * 4 + r] = acc[r];
 }
 
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// One V_MFMA_F32_16X16X4 with per-lane operands; raw accumulator out[lane * 4 + r].
+__global__ void mfma_probe_f32_kernel(const float* a, const float* b, float* out)
+{
+    const int l = threadIdx.x;
+    v4f acc = {0.f, 0.f, 0.f, 0.f};
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[l], b[l], acc, 0, 0, 0);
+    for (int r = 0; r < 4; ++r) out[l * 4 + r] = acc[r];
+}
+
 extern "C" {
+
+// a, b: 64 floats each (device); out: 256 floats (device).  One wave.
+int elmddm_test_mfma_layout_f32(const float* a, const float* b, float* out, void* stream)
+{
+    hipLaunchKernelGGL(mfma_probe_f32_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, a, b, out);
+    return hipGetLastError() == hipSuccess ? 0 : 7;
+}
+
+// Lower triangle of X^T X (n x n) with FP32 operands and accumulation.
+int elmddm_test_gram_f32(int n, int rows, const double* X, int ldx, long long sX, double* G, int ldg,
+                         long long sG, int batch, void* stream)
+{
+    gram_product_f32((hipStream_t)stream, n, rows, X, ldx, sX, G, ldg, sG, batch);
+    return hipGetLastError() == hipSuccess ? 0 : 7;
+}
 
 // a, b: 64 doubles each (device); out: 256 doubles (device).  One wave.
 int elmddm_test_mfma_layout(const double* a, const double* b, double* out, void* stream)

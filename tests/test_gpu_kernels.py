@@ -24,6 +24,8 @@ def hooks(gpu):
     L.elmddm_test_gram_strip.argtypes = [i32, i32, vp, i32, i64, vp, i32, i64, i32, vp]
     L.elmddm_test_trsm_strip.argtypes = [i32, i32, vp, i32, i64, vp, i32, i64, vp, i64, i32, vp]
     L.elmddm_test_potrf.argtypes = [vp, i32, i64, i32, i32, vp, i64, vp, i32, i64, vp, vp, i32, vp]
+    L.elmddm_test_mfma_layout_f32.argtypes = [vp, vp, vp, vp]
+    L.elmddm_test_gram_f32.argtypes = [i32, i32, vp, i32, i64, vp, i32, i64, i32, vp]
     return L
 
 
@@ -60,6 +62,51 @@ def test_mfma_f64_lane_layout(hooks):
     D = A @ B
     expect = np.array([[D[4 * r + l // 16, l % 16] for r in range(4)] for l in range(64)])
     assert np.array_equal(got, expect), got
+
+
+def test_mfma_f32_lane_layout(hooks):
+    """The FP32 Gram assumes: lane l holds A[l%16][l/16], B[l/16][l%16], and
+    accumulator element r of lane l is D[4 (l/16) + r][l%16]."""
+    import torch
+    rng = np.random.default_rng(1)
+    A = rng.integers(-4, 5, (16, 4)).astype(np.float32)
+    B = rng.integers(-4, 5, (4, 16)).astype(np.float32)
+    lanes = np.arange(64)
+    da, db = _dev(A[lanes % 16, lanes // 16]), _dev(B[lanes // 16, lanes % 16])
+    out = torch.zeros(256, dtype=torch.float32, device="cuda:0")
+    assert hooks.elmddm_test_mfma_layout_f32(_p(da), _p(db), _p(out), _stream()) == 0
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().reshape(64, 4)
+    D = A @ B
+    expect = np.array([[D[4 * (l // 16) + r, l % 16] for r in range(4)] for l in range(64)])
+    assert np.array_equal(got, expect), got
+
+
+@pytest.mark.parametrize("n,rows,batch", [(400, 1856, 2), (100, 520, 3), (37, 70, 2)])
+def test_gram_f32_within_float32_bound(hooks, n, rows, batch):
+    """FP32 operands and accumulation: every lower entry within the classical
+    bound (rows + 2) u32 (|X|^T |X|) of the exact Gram, and visibly not FP64."""
+    import torch
+    rng = np.random.default_rng(n + 3 * rows)
+    ldx, ldg = rows + 8, n + 5
+    X = rng.standard_normal((batch, n + 1, ldx))
+    dX = _dev(X)
+    dG = torch.zeros(batch * (n + 1) * ldg, dtype=torch.float64, device="cuda:0")
+    st = hooks.elmddm_test_gram_f32(n, rows, _p(dX), ldx, (n + 1) * ldx, _p(dG), ldg, (n + 1) * ldg, batch,
+                                    _stream())
+    assert st == 0
+    torch.cuda.synchronize()
+    G = dG.cpu().numpy().reshape(batch, n + 1, ldg)
+    mask = np.tril(np.ones((n, n), bool))
+    worst = 0.0
+    for z in range(batch):
+        Xz = X[z, :n, :rows].T
+        ref = Xz.T @ Xz
+        bound = (rows + 2) * 2.0**-24 * (np.abs(Xz).T @ np.abs(Xz))
+        err = np.abs(G[z, :n, :n].T - ref)
+        assert np.all(np.where(mask, err <= bound, True))
+        worst = max(worst, np.where(mask, err / np.abs(ref).max(), 0).max())
+    assert worst > 1e-12
 
 
 def ref_gemm(ta, tb, kmode, lower, M, N, K, alpha, A, B, beta, C):
