@@ -182,6 +182,26 @@ elmddm_status elmddm_assemble(elmddm_plan* plan, const double* W, const double* 
 elmddm_status elmddm_plan_keep_schur(elmddm_plan* plan, int32_t keep);
 elmddm_status elmddm_get_schur(elmddm_plan* plan, double* S, double* rhs, void* stream);
 
+/* Further right-hand sides with cached factors (plans with batch 1).  After
+ * an elmddm_solve, the plan's workspace holds every factor that depends on
+ * the hidden layer (the CholeskyQR factors of each K^s, the Schur matrix's
+ * envelope Cholesky factor); a new source f and boundary data g only change
+ * the F column of eq. nonoverlap_discrete.  elmddm_solve_rhs repeats, for
+ * nrhs such columns at once, h = Q^T F, the Schur right-hand side g of
+ * eq. schur, the two triangular solves with the factor of S and the local
+ * back-solve, and gives the same result as elmddm_solve with that data.
+ *   f [nrhs][nsub][q_x*q_y]  sources at the interior points
+ *   g [nrhs][n_boundary]     Dirichlet data (NULL: zero boundary data)
+ *   u_gamma [nrhs][n_interface]  output
+ *   c [nrhs][nsub][neurons]  output (NULL: skip the local back-solve)
+ * elmddm_plan_reserve_rhs allocates the workspace for up to max_rhs columns
+ * per pass (1..4096; larger nrhs are processed in passes of max_rhs).
+ * Fails with INVALID_ARG if no solve has been enqueued since the plan was
+ * created or autotuned, UNSUPPORTED for plans with batch > 1. */
+elmddm_status elmddm_plan_reserve_rhs(elmddm_plan* plan, int32_t max_rhs);
+elmddm_status elmddm_solve_rhs(elmddm_plan* plan, int32_t nrhs, const double* f, const double* g,
+                               double* u_gamma, double* c, void* stream);
+
 /* Precision mode of later solves on this plan.
  *  ELMDDM_MODE_FP64 (default): every product in float64.
  *  ELMDDM_MODE_MIXED: the Gram matrices of the first CholeskyQR pass are

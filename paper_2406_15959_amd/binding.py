@@ -35,7 +35,7 @@ EXPORTED = [
     "elmddm_plan_create", "elmddm_plan_create_batch", "elmddm_plan_destroy", "elmddm_plan_sizes", "elmddm_points",
     "elmddm_solve", "elmddm_solve_info", "elmddm_eval", "elmddm_assemble",
     "elmddm_plan_keep_schur", "elmddm_get_schur", "elmddm_set_timing", "elmddm_stage_times", "elmddm_pass_times",
-    "elmddm_autotune", "elmddm_plan_set_mode",
+    "elmddm_autotune", "elmddm_plan_set_mode", "elmddm_plan_reserve_rhs", "elmddm_solve_rhs",
     "elmddm_status_string", "elmddm_last_error",
 ]
 
@@ -94,6 +94,8 @@ def lib():
         L.elmddm_set_timing.argtypes = [vp, i32]
         L.elmddm_autotune.argtypes = [vp, vp, ctypes.POINTER(i32)]
         L.elmddm_plan_set_mode.argtypes = [vp, i32]
+        L.elmddm_plan_reserve_rhs.argtypes = [vp, i32]
+        L.elmddm_solve_rhs.argtypes = [vp, i32, dp, dp, dp, dp, vp]
         L.elmddm_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]
         L.elmddm_pass_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]
         L.elmddm_status_string.argtypes = [i32]
@@ -178,6 +180,13 @@ class Plan:
     def assemble(self, W, b, f, g, coef, K, A, F):
         _check(lib().elmddm_assemble(self._h, _ptr(W), _ptr(b), _ptr(f), _ptr(g), _ptr(coef),
                                      _ptr(K), _ptr(A), _ptr(F), _stream()))
+
+    def reserve_rhs(self, max_rhs):
+        _check(lib().elmddm_plan_reserve_rhs(self._h, max_rhs))
+
+    def solve_rhs(self, nrhs, f, g, u_gamma, c=None):
+        """nrhs further right-hand sides with the factors of the last solve."""
+        _check(lib().elmddm_solve_rhs(self._h, nrhs, _ptr(f), _ptr(g), _ptr(u_gamma), _ptr(c), _stream()))
 
     def set_mode(self, mode):
         """MODE_FP64 or MODE_MIXED for later solves."""

@@ -170,4 +170,13 @@ void envelope_potrf(hipStream_t st, double* A, int lda, long long sA, double* Lo
 void init_info(hipStream_t st, DevInfo* info);
 void check_finite(hipStream_t st, const double* v, long long count, DevInfo* info);
 
+// Further right-hand sides with cached factors.
+void rhs_assemble(hipStream_t st, const RowTable& rows, int ldx, int nrows, int ldf, const double* f,
+                  const double* g, int N, int nrhs, long long nf, long long nbnd, double* Fr);
+void trsv_lower_block(hipStream_t st, const double* L, int ld, long long sL, int j0, int br, int r1,
+                      const double* Dinv, long long sD, double* y, long long sY, int batch);
+void backsolve_rhs_multi(hipStream_t st, int N, int n, int kpad, const double* X, int ldx, long long sX,
+                         int mI, const int32_t* gidx, const double* u, long long nG, const double* H,
+                         double* V, int nrhs);
+
 }  // namespace elmddm

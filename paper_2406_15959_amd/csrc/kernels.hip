@@ -1479,3 +1479,129 @@ void check_finite(hipStream_t st, const double* v, long long count, DevInfo* inf
 }
 
 }  // namespace elmddm
+
+// ---------------------------------------------------------------------------
+// Solves for further right-hand sides with the factors of an earlier solve
+// (same hidden layer, new source f and boundary data g): only the F column
+// of eq. nonoverlap_discrete changes, so h = Q^T F, the Schur rhs, the two
+// triangular solves on S and the back-solve are repeated.
+// ---------------------------------------------------------------------------
+namespace elmddm {
+
+// Fr[s][r][row] = F column of subdomain s for rhs r (rows [0, rows)).
+__global__ __launch_bounds__(256) void rhs_assemble_kernel(RowTable rows, int ldx, int nrows, int ldf,
+                                                           const double* f, const double* g, int N,
+                                                           int nrhs, long long nf, long long nbnd,
+                                                           double* Fr)
+{
+    const int row = blockIdx.x * 256 + threadIdx.x;
+    const int s = blockIdx.y;
+    const int r = blockIdx.z;
+    if (row >= nrows) return;
+    const long long ri = (long long)s * ldx + row;
+    const int kind = rows.kind[ri];
+    double v = 0.0;
+    if (kind == ROW_INTERIOR) v = f[r * nf + rows.src[ri]];
+    else if (kind == ROW_BOUNDARY && g) v = g[r * nbnd + rows.src[ri]];
+    Fr[((long long)s * nrhs + r) * ldf + row] = v;
+}
+
+void rhs_assemble(hipStream_t st, const RowTable& rows, int ldx, int nrows, int ldf, const double* f,
+                  const double* g, int N, int nrhs, long long nf, long long nbnd, double* Fr)
+{
+    dim3 grid((nrows + 255) / 256, N, nrhs);
+    hipLaunchKernelGGL(rhs_assemble_kernel, grid, dim3(256), 0, st, rows, ldx, nrows, ldf, f, g, N, nrhs,
+                       nf, nbnd, Fr);
+}
+
+// Forward substitution L y = g over one block row of up to 256 rows
+// [j0, j0 + br) of the envelope factor (diagonal 64-blocks through their
+// inverses Dinv, off-diagonal tiles in L): every workgroup solves the block
+// (four 64-row sub-blocks, right-looking inside the block), workgroup 0
+// stores it, and each workgroup then subtracts L[r, block] y_block from its
+// share of the rows r in [j0 + br, r1) (one thread per row, coalesced along
+// the columns of L).  Batch index z: y += z sY, L += z sL, Dinv += z sD.
+__global__ __launch_bounds__(256) void trsv_l_block_kernel(const double* L, int ld, long long sL, int j0,
+                                                           int br, int r1, const double* Dinv,
+                                                           long long sD, double* y, long long sY)
+{
+    {
+        const long long zb = blockIdx.y;
+        L += zb * sL;
+        Dinv += zb * sD;
+        y += zb * sY;
+    }
+    __shared__ double yb[256], ub[256];
+    const int tid = threadIdx.x;
+    yb[tid] = tid < br ? y[j0 + tid] : 0.0;
+    ub[tid] = 0.0;
+    __syncthreads();
+    const int nsub = (br + 63) / 64;
+    for (int sb = 0; sb < nsub; ++sb) {
+        const int s0 = 64 * sb, sl = (br - s0) < 64 ? (br - s0) : 64;
+        if (tid < sl) {
+            const double* D = Dinv + (long long)((j0 + s0) / 64) * 64 * 64;
+            double acc = 0.0;
+            for (int k = 0; k <= tid; ++k) acc += D[k * 64 + tid] * yb[s0 + k];
+            ub[s0 + tid] = acc;
+        }
+        __syncthreads();
+        if (tid >= s0 + 64 && tid < br) {
+            double acc = 0.0;
+            for (int t = 0; t < sl; ++t) acc += L[(long long)(j0 + s0 + t) * ld + j0 + tid] * ub[s0 + t];
+            yb[tid] -= acc;
+        }
+        __syncthreads();
+    }
+    if (blockIdx.x == 0 && tid < br) y[j0 + tid] = ub[tid];
+    for (int r = j0 + br + blockIdx.x * 256 + tid; r < r1; r += gridDim.x * 256) {
+        double acc = 0.0;
+        for (int c = 0; c < br; ++c) acc += L[(long long)(j0 + c) * ld + r] * ub[c];
+        y[r] -= acc;
+    }
+}
+
+void trsv_lower_block(hipStream_t st, const double* L, int ld, long long sL, int j0, int br, int r1,
+                      const double* Dinv, long long sD, double* y, long long sY, int batch)
+{
+    const int rows = r1 - j0 - br;
+    int nb = (rows + 255) / 256;
+    nb = nb < 1 ? 1 : nb;
+    hipLaunchKernelGGL(trsv_l_block_kernel, dim3(nb, batch), dim3(256), 0, st, L, ld, sL, j0, br, r1,
+                       Dinv, sD, y, sY);
+}
+
+// V[s][r][col] = H[s][r][col] + sum_i Q_Gamma,s[i][col] u_r[gidx_s[i]]: the
+// right-hand side of the local back-solve for nrhs interface vectors.
+__global__ __launch_bounds__(256) void bs_rhs_multi_kernel(int n, int kpad, const double* X, int ldx,
+                                                           long long sX, int mI, const int32_t* gidx,
+                                                           const double* u, long long nG,
+                                                           const double* H, double* V, int nrhs)
+{
+    const int s = blockIdx.y;
+    const int r = blockIdx.z;
+    const int lane = threadIdx.x & 63;
+    const int col = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (col >= n) return;
+    const double* xc = X + s * sX + (long long)col * ldx + mI;
+    const double* ur = u + r * nG;
+    double acc = 0.0;
+    for (int i = lane; i < kpad; i += 64) {
+        const int gi = gidx[s * kpad + i];
+        if (gi >= 0) acc += xc[i] * ur[gi];
+    }
+    acc = wave_sum(acc);
+    const long long o = ((long long)s * nrhs + r) * n + col;
+    if (lane == 0) V[o] = acc + H[o];
+}
+
+void backsolve_rhs_multi(hipStream_t st, int N, int n, int kpad, const double* X, int ldx, long long sX,
+                         int mI, const int32_t* gidx, const double* u, long long nG, const double* H,
+                         double* V, int nrhs)
+{
+    dim3 grid((n + 3) / 4, N, nrhs);
+    hipLaunchKernelGGL(bs_rhs_multi_kernel, grid, dim3(256), 0, st, n, kpad, X, ldx, sX, mI, gidx, u, nG,
+                       H, V, nrhs);
+}
+
+}  // namespace elmddm

@@ -77,6 +77,11 @@ struct elmddm_plan {
     bool schur_valid = false;
     hipStream_t last_stream = nullptr;
     bool solved = false;
+    bool factors_valid = false;   // the workspace holds the factors of the last solve
+    // further right-hand sides (elmddm_plan_reserve_rhs / elmddm_solve_rhs)
+    int rhs_cap = 0;
+    double *Fr = nullptr, *Tm = nullptr, *Hm = nullptr, *Ph = nullptr, *abufR = nullptr;
+    double *yR = nullptr, *uR = nullptr, *Vm = nullptr;
     // stage timing
     bool timing = false;
     hipEvent_t ev[ELMDDM_NUM_STAGES + 1] = {};
@@ -686,6 +691,7 @@ elmddm_status elmddm_solve(elmddm_plan* P, const double* W, const double* b, con
     if (P->timing) P->harvest();
     P->last_stream = st;
     P->solved = true;
+    P->factors_valid = false;
     const int N = P->NT, n = P->n, ldx = P->ldx, ldg = P->ldg;
     const int B = P->B;
     const long long sS = (long long)P->lds * std::max(P->nG, 1);
@@ -784,12 +790,104 @@ elmddm_status elmddm_solve(elmddm_plan* P, const double* W, const double* b, con
     check_finite(st, c, nc, P->d_info);
     if (P->nG > 0) check_finite(st, u_gamma, (long long)B * P->nG, P->d_info);
     if (P->timing) P->ev_pending = true;
-    return check_launch("back-solve");
+    est = check_launch("back-solve");
+    P->factors_valid = est == ELMDDM_OK;
+    return est;
+}
+
+elmddm_status elmddm_plan_reserve_rhs(elmddm_plan* P, int32_t max_rhs)
+{
+    if (!P) return fail(ELMDDM_INVALID_ARG, "NULL plan");
+    if (P->B != 1) return fail(ELMDDM_UNSUPPORTED, "further right-hand sides need a plan with batch 1");
+    if (max_rhs < 1 || max_rhs > 4096) return fail(ELMDDM_INVALID_ARG, "max_rhs must be in [1, 4096]");
+    if (max_rhs <= P->rhs_cap) return ELMDDM_OK;
+    for (double** q : {&P->Fr, &P->Tm, &P->Hm, &P->Ph, &P->abufR, &P->yR, &P->uR, &P->Vm}) {
+        if (*q) {
+            P->allocs.erase(std::find(P->allocs.begin(), P->allocs.end(), (void*)*q));
+            (void)hipFree(*q);
+            *q = nullptr;
+        }
+    }
+    P->rhs_cap = 0;
+    const size_t R = max_rhs, N = P->N, n = P->n, nGm = std::max(P->nG, 1);
+    elmddm_status st;
+    if ((st = P->dalloc(&P->Fr, N * R * P->gram_rows)) != ELMDDM_OK) return st;
+    if ((st = P->dalloc(&P->Tm, N * R * n)) != ELMDDM_OK) return st;
+    if ((st = P->dalloc(&P->Hm, N * R * n)) != ELMDDM_OK) return st;
+    if ((st = P->dalloc(&P->Vm, N * R * n)) != ELMDDM_OK) return st;
+    if ((st = P->dalloc(&P->Ph, R * N * P->ldp)) != ELMDDM_OK) return st;
+    if ((st = P->dalloc(&P->abufR, R * std::max(P->nE, 1) * P->mg)) != ELMDDM_OK) return st;
+    if ((st = P->dalloc(&P->yR, R * nGm)) != ELMDDM_OK) return st;
+    if ((st = P->dalloc(&P->uR, R * nGm)) != ELMDDM_OK) return st;
+    P->rhs_cap = max_rhs;
+    return ELMDDM_OK;
+}
+
+elmddm_status elmddm_solve_rhs(elmddm_plan* P, int32_t nrhs, const double* f, const double* g,
+                               double* u_gamma, double* c, void* stream)
+{
+    if (!P) return fail(ELMDDM_INVALID_ARG, "NULL plan");
+    if (P->B != 1) return fail(ELMDDM_UNSUPPORTED, "further right-hand sides need a plan with batch 1");
+    if (nrhs < 0 || !f) return fail(ELMDDM_INVALID_ARG, "bad nrhs or NULL f");
+    if (P->nG > 0 && !u_gamma) return fail(ELMDDM_INVALID_ARG, "u_gamma is NULL");
+    if (!P->factors_valid) return fail(ELMDDM_INVALID_ARG, "no factors: call elmddm_solve on this plan first");
+    if (P->rhs_cap < 1) return fail(ELMDDM_INVALID_ARG, "call elmddm_plan_reserve_rhs first");
+    hipStream_t st = (hipStream_t)stream;
+    const int N = P->N, n = P->n, ldx = P->ldx, ldg = P->ldg, ldf = P->gram_rows, nG = P->nG;
+    const int ldp = P->ldp, mg = P->mg, kp = P->kpad;
+    const long long nf = (long long)N * P->q2;
+    // after a solve: X0 = Q2 (all rows), X1 rows [mI, ldx) = Q3 interface rows, h row, Z^T rows
+    const double* Q2 = P->X0;
+    const double* X1 = P->X1;
+    for (int r0 = 0; r0 < nrhs; r0 += P->rhs_cap) {
+        const int R = std::min(P->rhs_cap, nrhs - r0);
+        rhs_assemble(st, row_table(P), ldx, P->gram_rows, ldf, f + r0 * nf, g ? g + r0 * P->nB : nullptr, N, R,
+                     nf, P->nB, P->Fr);
+        // h = L3^{-1} Q2^T F
+        gemm_f64(st, true, false, 0, false, n, R, P->gram_rows, 1.0, Q2, ldx, P->sX, P->Fr, ldf,
+                 (long long)R * ldf, 0.0, P->Tm, n, (long long)R * n, N);
+        gemm_f64(st, false, false, 0, false, n, R, n, 1.0, P->Linv[2], ldg, P->sL, P->Tm, n, (long long)R * n,
+                 0.0, P->Hm, n, (long long)R * n, N);
+        if (nG > 0) {
+            // [q; a] = [Q_Gamma^T h; Z h] per subdomain, laid out [rhs][subdomain][ldp]
+            gemm_f64(st, false, false, 0, false, 2 * kp + 16, R, n, 1.0, X1 + P->mI, ldx, P->sX, P->Hm, n,
+                     (long long)R * n, 0.0, P->Ph, N * ldp, ldp, N);
+            schur_avec(st, P->nE, P->d_adesc, P->Ph, ldp, ldp, kp + 16, 0, mg, P->abufR, N, R);
+            schur_rhs(st, P->nE, mg, P->d_qdesc, P->d_gptr, P->d_gdesc, P->Ph, ldp, ldp, 0, P->Mbuf, P->abufR,
+                      P->yR, 1, P->d_perm, N, 0, (long long)P->nE * mg, nG, R);
+            // L y = g, then L^T u = y, with the envelope factor of S
+            const int BR = 4 * NB;
+            for (int j0 = 0; j0 < nG; j0 += BR) {
+                const int br = std::min(BR, nG - j0);
+                const int r1 = std::max(j0 + br, P->rend[(j0 + br - 1) / NB]);
+                trsv_lower_block(st, P->SL, P->lds, 0, j0, br, r1, P->DinvS, 0, P->yR, nG, R);
+            }
+            for (int j0 = (nG - 1) / BR * BR; j0 >= 0; j0 -= BR) {
+                const int br = std::min(BR, nG - j0);
+                trsv_lower_t_block(st, P->SL, P->lds, 0, j0, br, P->kbeg[j0 / NB], P->DinvS, 0, P->yR, P->uR,
+                                   nG, R);
+            }
+            unpermute(st, P->nE, mg, P->d_perm, P->uR, u_gamma + (long long)r0 * nG, R);
+        }
+        if (c) {
+            // c = Linv1^T Linv2^T Linv3^T (h + Q_Gamma^T u)
+            backsolve_rhs_multi(st, N, n, kp, X1, ldx, P->sX, P->mI, P->d_gidx,
+                                nG > 0 ? u_gamma + (long long)r0 * nG : nullptr, nG, P->Hm, P->Vm, R);
+            gemm_f64(st, true, false, 0, false, n, R, n, 1.0, P->Linv[2], ldg, P->sL, P->Vm, n, (long long)R * n,
+                     0.0, P->Tm, n, (long long)R * n, N);
+            gemm_f64(st, true, false, 0, false, n, R, n, 1.0, P->Linv[1], ldg, P->sL, P->Tm, n, (long long)R * n,
+                     0.0, P->Vm, n, (long long)R * n, N);
+            gemm_f64(st, true, false, 0, false, n, R, n, 1.0, P->Linv[0], ldg, P->sL, P->Vm, n, (long long)R * n,
+                     0.0, c + (long long)r0 * N * n, N * n, n, N);
+        }
+    }
+    return check_launch("solve_rhs");
 }
 
 elmddm_status elmddm_autotune(elmddm_plan* P, void* stream, int32_t* choice)
 {
     if (!P) return fail(ELMDDM_INVALID_ARG, "NULL plan");
+    P->factors_valid = false;
     hipStream_t st = (hipStream_t)stream;
     const int N = P->NT, n = P->n, ldx = P->ldx, ldg = P->ldg;
     // timing only: operand values do not matter, but must be finite

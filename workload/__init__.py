@@ -166,3 +166,71 @@ def sample_data(problem: Problem, interior_xy, boundary_xy):
     if problem.op == OP_VARCOEF:
         coef = np.stack(coefficient(problem, interior_xy[:, 0], interior_xy[:, 1]))
     return f, g, coef
+
+
+# ---------------------------------------------------------------------------
+# Random Fourier-series sources on the unit square (the learned-interface
+# workload): f = sum_{k1,k2=1..M} alpha_k sin(pi k1 x) sin(pi k2 y) with
+# alpha_k ~ N(0, 1/(1 + k1^2 + k2^2)); u = 0 on the boundary; the exact
+# Poisson solution is sum alpha_k sin sin / (pi^2 (k1^2 + k2^2)).
+# ---------------------------------------------------------------------------
+
+# 16x16 subdomains of the 8x8 case's resolution: 400 neurons, U[-4,4], 40x40
+# interior points and 40 points per edge (19200 interface unknowns).
+CONFIG_16x16 = Problem(nsub_x=16, nsub_y=16, neurons=400, q_x=40, q_y=40,
+                       m_bdry_edge=40, m_ifc_edge=40, R=4.0)
+
+
+def _modes(M):
+    k = np.arange(1, M + 1, dtype=np.float64)
+    return k, 1.0 + k[:, None] ** 2 + k[None, :] ** 2
+
+
+def fourier_coeffs(seed: int, modes: int = 32, count: int = 1):
+    """count coefficient arrays alpha of shape (count, modes, modes), indexed [k1-1, k2-1]."""
+    _, w = _modes(modes)
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((count, modes, modes)) / np.sqrt(w)
+
+
+def fourier_features(alpha):
+    """Network input: alpha row-major, each mode scaled by sqrt(1 + |k|^2) (unit variance)."""
+    alpha = np.asarray(alpha, dtype=np.float64)
+    M = alpha.shape[-1]
+    _, w = _modes(M)
+    return (alpha * np.sqrt(w)).reshape(alpha.shape[0], M * M)
+
+
+def _sine_table(v, M):
+    k, _ = _modes(M)
+    return np.sin(math.pi * np.outer(v, k))
+
+
+def fourier_series_at(alpha, x, y, scale=None):
+    """sum_k alpha_k s_k sin(pi k1 x) sin(pi k2 y) at points (x, y) for every
+    coefficient array in alpha (count, M, M); returns (count, npts).  Points on
+    a tensor grid (any order) are evaluated through the grid."""
+    alpha = np.asarray(alpha, dtype=np.float64)
+    if scale is not None:
+        alpha = alpha * scale
+    M = alpha.shape[-1]
+    ux, ix = np.unique(np.asarray(x, dtype=np.float64), return_inverse=True)
+    uy, iy = np.unique(np.asarray(y, dtype=np.float64), return_inverse=True)
+    Sx, Sy = _sine_table(ux, M), _sine_table(uy, M)
+    out = np.empty((alpha.shape[0], len(ix)))
+    for c in range(alpha.shape[0]):
+        grid = (Sx @ alpha[c]) @ Sy.T          # grid[i, j] = f(ux[i], uy[j])
+        out[c] = grid[ix, iy]
+    return out
+
+
+def fourier_source(alpha, x, y):
+    """Source f of every coefficient array (Poisson: f = -Lap u)."""
+    return fourier_series_at(alpha, x, y)
+
+
+def fourier_exact(alpha, x, y):
+    """Exact Poisson solution of every coefficient array."""
+    M = np.asarray(alpha).shape[-1]
+    _, w = _modes(M)
+    return fourier_series_at(alpha, x, y, scale=1.0 / (math.pi ** 2 * (w - 1.0)))
