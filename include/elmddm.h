@@ -202,6 +202,27 @@ elmddm_status elmddm_plan_reserve_rhs(elmddm_plan* plan, int32_t max_rhs);
 elmddm_status elmddm_solve_rhs(elmddm_plan* plan, int32_t nrhs, const double* f, const double* g,
                                double* u_gamma, double* c, void* stream);
 
+/* The right-hand side g of eq. schur (interface order) for nrhs further
+ * sources with the factors of the last solve (same conditions and layouts
+ * as elmddm_solve_rhs): rhs [nrhs][n_interface], device. */
+elmddm_status elmddm_schur_rhs(elmddm_plan* plan, int32_t nrhs, const double* f, const double* g,
+                               double* rhs, void* stream);
+
+/* Conjugate gradients on the interface system S u = rhs (Section 3; the
+ * paper's interface solver), with S the Schur matrix of the last solve, kept
+ * by elmddm_plan_keep_schur(plan, 1) before that solve.  u [nrhs][n_interface]
+ * (device) holds the initial guesses on entry and the iterates on return.
+ * Each system stops when ||rhs - S u|| <= tol ||rhs|| (checked every
+ * iteration; the host polls every 16 iterations) or after maxit iterations.
+ * iters (host int32 [nrhs], or NULL) receives the iteration counts, relres
+ * (host double [nrhs], or NULL) the final relative residuals
+ * ||rhs - S u|| / ||rhs|| as tracked by the recurrence (maxit = 0: the
+ * residual of the initial guess, computed directly).
+ * Synchronises the stream; returns NOT_CONVERGED if any system did not reach
+ * tol.  Needs elmddm_plan_reserve_rhs (passes of up to max_rhs systems). */
+elmddm_status elmddm_interface_cg(elmddm_plan* plan, int32_t nrhs, const double* rhs, double* u, double tol,
+                                  int32_t maxit, int32_t* iters, double* relres, void* stream);
+
 /* Precision mode of later solves on this plan.
  *  ELMDDM_MODE_FP64 (default): every product in float64.
  *  ELMDDM_MODE_MIXED: the Gram matrices of the first CholeskyQR pass are
@@ -248,6 +269,63 @@ elmddm_status elmddm_stage_times(elmddm_plan* plan, double* ms, int32_t* solves)
  * ms[3 p + 1] Cholesky + inverses, ms[3 p + 2] triangular solve of pass
  * p + 1 (p = 0, 1, 2), in milliseconds summed over the timed solves. */
 elmddm_status elmddm_pass_times(elmddm_plan* plan, double* ms, int32_t* solves);
+
+/* ------------------------------------------------------------------------
+ * Learned interface variable (not part of the paper's method).  For a fixed
+ * geometry and hidden layer, u_Gamma of eq. schur depends only on the source;
+ * a small MLP
+ *     y = W3 GELU(W2 GELU(W1 x + b1) + b2) + b3,   GELU(z) = z Phi(z) (exact),
+ * trained on (source features -> u_Gamma) pairs produced by the method
+ * itself, predicts u_Gamma as an initial guess for the interface solve.
+ * FP32 weights and activations on the matrix cores.
+ *
+ * Layout: x [batch][in_dim], y and targets [batch][out_dim] (float32, device,
+ * one contiguous row per sample).  Flat parameter vector (float32, device,
+ * elmddm_mlp_num_params entries): W1 (hidden x in_dim, column-major), b1,
+ * W2 (hidden x hidden), b2, W3 (out_dim x hidden), b3.  The library draws
+ * no random numbers: initial weights come in through elmddm_mlp_set_params,
+ * the sample order of training through `order`.
+ * ------------------------------------------------------------------------ */
+typedef struct elmddm_mlp elmddm_mlp;
+
+/* Allocate a network and its workspace for batches of up to max_batch
+ * samples (device memory, released by elmddm_mlp_destroy). */
+elmddm_status elmddm_mlp_create(int32_t in_dim, int32_t hidden, int32_t out_dim, int32_t max_batch,
+                                elmddm_mlp** mlp);
+elmddm_status elmddm_mlp_destroy(elmddm_mlp* mlp);
+elmddm_status elmddm_mlp_num_params(const elmddm_mlp* mlp, int64_t* count);
+
+/* Copy parameters in (and reset the Adam state) / out; device buffers. */
+elmddm_status elmddm_mlp_set_params(elmddm_mlp* mlp, const float* params, void* stream);
+elmddm_status elmddm_mlp_get_params(const elmddm_mlp* mlp, float* params, void* stream);
+
+/* Network output y for a batch x. */
+elmddm_status elmddm_mlp_forward(elmddm_mlp* mlp, int32_t batch, const float* x, float* y, void* stream);
+
+/* Mean squared error L = sum (y - t)^2 / (batch out_dim) into *loss (device
+ * float) and its gradient with respect to the flat parameters (kept for
+ * elmddm_mlp_adam_step; also copied to grad if not NULL). */
+elmddm_status elmddm_mlp_loss_grad(elmddm_mlp* mlp, int32_t batch, const float* x, const float* t,
+                                   float* loss, float* grad, void* stream);
+
+/* One Adam step (bias-corrected moments) with the gradient of the last
+ * elmddm_mlp_loss_grad. */
+elmddm_status elmddm_mlp_adam_step(elmddm_mlp* mlp, float lr, float beta1, float beta2, float eps,
+                                   void* stream);
+
+/* `steps` training steps on the samples X [nsamples][in_dim], targets T
+ * [nsamples][out_dim]: step k uses the samples order[k*batch .. k*batch+batch)
+ * (int32, device; an index outside [0, nsamples) reads a zero sample),
+ * then one Adam step with learning rate
+ * lr (1 + cos(pi k / steps)) / 2.  losses (device float [steps], or NULL)
+ * receives each step's loss before its update. */
+elmddm_status elmddm_mlp_train(elmddm_mlp* mlp, int32_t nsamples, const float* X, const float* T,
+                               const int32_t* order, int32_t steps, int32_t batch, float lr, float beta1,
+                               float beta2, float eps, float* losses, void* stream);
+
+/* Prediction in float64: out [batch][out_dim] = scale * y. */
+elmddm_status elmddm_mlp_predict(elmddm_mlp* mlp, int32_t batch, const float* x, double scale, double* out,
+                                 void* stream);
 
 const char* elmddm_status_string(elmddm_status status);
 const char* elmddm_last_error(void);

@@ -36,6 +36,10 @@ EXPORTED = [
     "elmddm_solve", "elmddm_solve_info", "elmddm_eval", "elmddm_assemble",
     "elmddm_plan_keep_schur", "elmddm_get_schur", "elmddm_set_timing", "elmddm_stage_times", "elmddm_pass_times",
     "elmddm_autotune", "elmddm_plan_set_mode", "elmddm_plan_reserve_rhs", "elmddm_solve_rhs",
+    "elmddm_schur_rhs", "elmddm_interface_cg",
+    "elmddm_mlp_create", "elmddm_mlp_destroy", "elmddm_mlp_num_params", "elmddm_mlp_set_params",
+    "elmddm_mlp_get_params", "elmddm_mlp_forward", "elmddm_mlp_loss_grad", "elmddm_mlp_adam_step",
+    "elmddm_mlp_train", "elmddm_mlp_predict",
     "elmddm_status_string", "elmddm_last_error",
 ]
 
@@ -96,8 +100,22 @@ def lib():
         L.elmddm_plan_set_mode.argtypes = [vp, i32]
         L.elmddm_plan_reserve_rhs.argtypes = [vp, i32]
         L.elmddm_solve_rhs.argtypes = [vp, i32, dp, dp, dp, dp, vp]
+        L.elmddm_schur_rhs.argtypes = [vp, i32, dp, dp, dp, vp]
+        L.elmddm_interface_cg.argtypes = [vp, i32, dp, dp, ctypes.c_double, i32, ctypes.POINTER(i32),
+                                          ctypes.POINTER(ctypes.c_double), vp]
         L.elmddm_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]
         L.elmddm_pass_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]
+        f32 = ctypes.c_float
+        L.elmddm_mlp_create.argtypes = [i32, i32, i32, i32, ctypes.POINTER(vp)]
+        L.elmddm_mlp_destroy.argtypes = [vp]
+        L.elmddm_mlp_num_params.argtypes = [vp, ctypes.POINTER(i64)]
+        L.elmddm_mlp_set_params.argtypes = [vp, dp, vp]
+        L.elmddm_mlp_get_params.argtypes = [vp, dp, vp]
+        L.elmddm_mlp_forward.argtypes = [vp, i32, dp, dp, vp]
+        L.elmddm_mlp_loss_grad.argtypes = [vp, i32, dp, dp, dp, dp, vp]
+        L.elmddm_mlp_adam_step.argtypes = [vp, f32, f32, f32, f32, vp]
+        L.elmddm_mlp_train.argtypes = [vp, i32, dp, dp, dp, i32, i32, f32, f32, f32, f32, dp, vp]
+        L.elmddm_mlp_predict.argtypes = [vp, i32, dp, ctypes.c_double, dp, vp]
         L.elmddm_status_string.argtypes = [i32]
         L.elmddm_status_string.restype = ctypes.c_char_p
         L.elmddm_last_error.restype = ctypes.c_char_p
@@ -120,6 +138,15 @@ def _ptr(t):
     import torch
     assert isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous(), \
         "expected a contiguous float64 CUDA tensor"
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _ptr_t(t, dtype):
+    if t is None:
+        return None
+    import torch
+    assert isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous(), \
+        f"expected a contiguous {dtype} CUDA tensor"
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -188,6 +215,20 @@ class Plan:
         """nrhs further right-hand sides with the factors of the last solve."""
         _check(lib().elmddm_solve_rhs(self._h, nrhs, _ptr(f), _ptr(g), _ptr(u_gamma), _ptr(c), _stream()))
 
+    def schur_rhs(self, nrhs, f, g, rhs):
+        _check(lib().elmddm_schur_rhs(self._h, nrhs, _ptr(f), _ptr(g), _ptr(rhs), _stream()))
+
+    def interface_cg(self, nrhs, rhs, u, tol, maxit, check=True, with_residuals=False):
+        """CG on the kept S from the guesses in u; returns (status, iteration counts[, relative residuals])."""
+        its = (ctypes.c_int32 * max(nrhs, 1))()
+        res = (ctypes.c_double * max(nrhs, 1))()
+        st = lib().elmddm_interface_cg(self._h, nrhs, _ptr(rhs), _ptr(u), tol, maxit, its, res, _stream())
+        if check and st not in (OK, NOT_CONVERGED):
+            _check(st)
+        if with_residuals:
+            return st, list(its)[:nrhs], list(res)[:nrhs]
+        return st, list(its)[:nrhs]
+
     def set_mode(self, mode):
         """MODE_FP64 or MODE_MIXED for later solves."""
         _check(lib().elmddm_plan_set_mode(self._h, mode))
@@ -220,3 +261,61 @@ class Plan:
 
     def get_schur(self, S, rhs):
         _check(lib().elmddm_get_schur(self._h, _ptr(S), _ptr(rhs), _stream()))
+
+
+class MLP:
+    """Interface-variable MLP (FP32) owned by the HIP library."""
+
+    def __init__(self, in_dim, hidden, out_dim, max_batch):
+        self._h = ctypes.c_void_p()
+        self.max_batch = max_batch
+        _check(lib().elmddm_mlp_create(in_dim, hidden, out_dim, max_batch, ctypes.byref(self._h)))
+        n = ctypes.c_int64()
+        _check(lib().elmddm_mlp_num_params(self._h, ctypes.byref(n)))
+        self.num_params = n.value
+        self.dims = (in_dim, hidden, hidden, out_dim)
+
+    def close(self):
+        if self._h:
+            lib().elmddm_mlp_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        import torch
+        _check(lib().elmddm_mlp_set_params(self._h, _ptr_t(params, torch.float32), _stream()))
+
+    def get_params(self, out):
+        import torch
+        _check(lib().elmddm_mlp_get_params(self._h, _ptr_t(out, torch.float32), _stream()))
+
+    def forward(self, batch, x, y):
+        import torch
+        _check(lib().elmddm_mlp_forward(self._h, batch, _ptr_t(x, torch.float32), _ptr_t(y, torch.float32),
+                                        _stream()))
+
+    def loss_grad(self, batch, x, t, loss, grad=None):
+        import torch
+        f = torch.float32
+        _check(lib().elmddm_mlp_loss_grad(self._h, batch, _ptr_t(x, f), _ptr_t(t, f), _ptr_t(loss, f),
+                                          _ptr_t(grad, f), _stream()))
+
+    def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        _check(lib().elmddm_mlp_adam_step(self._h, lr, beta1, beta2, eps, _stream()))
+
+    def train(self, nsamples, X, T, order, steps, batch, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+              losses=None):
+        import torch
+        f = torch.float32
+        _check(lib().elmddm_mlp_train(self._h, nsamples, _ptr_t(X, f), _ptr_t(T, f), _ptr_t(order, torch.int32),
+                                      steps, batch, lr, beta1, beta2, eps, _ptr_t(losses, f), _stream()))
+
+    def predict(self, batch, x, scale, out):
+        import torch
+        _check(lib().elmddm_mlp_predict(self._h, batch, _ptr_t(x, torch.float32), scale,
+                                        _ptr_t(out, torch.float64), _stream()))

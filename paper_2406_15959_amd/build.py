@@ -13,8 +13,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libelmddm.so")
 TEST_LIB = os.path.join(PKG, "libelmddm_testhooks.so")
-SOURCES = ["kernels.hip", "linalg.cpp", "plan.cpp", "testhooks.cpp"]
-LIB_OBJS = ["kernels", "linalg", "plan"]
+SOURCES = ["kernels.hip", "linalg.cpp", "plan.cpp", "mlp.hip", "testhooks.cpp"]
+LIB_OBJS = ["kernels", "linalg", "plan", "mlp"]
 TEST_OBJS = ["kernels", "linalg", "testhooks"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -6,6 +6,9 @@
 
 namespace elmddm {
 
+// Set the message returned by elmddm_last_error() on this thread; returns status.
+int record_error(int status, const char* msg);
+
 // Row kinds of the per-subdomain row table (one entry per row of X).
 enum RowKind : int32_t {
     ROW_ZERO = 0,       // padding row: all zero
@@ -178,5 +181,14 @@ void trsv_lower_block(hipStream_t st, const double* L, int ld, long long sL, int
 void backsolve_rhs_multi(hipStream_t st, int N, int n, int kpad, const double* X, int ldx, long long sX,
                          int mI, const int32_t* gidx, const double* u, long long nG, const double* H,
                          double* V, int nrhs);
+
+// Conjugate gradients on the kept interface matrix.
+void permute(hipStream_t st, int nE, int mg, const int32_t* perm, const double* u, double* up, int nrhs);
+void band_symv(hipStream_t st, int n, const double* S, int lds, const int32_t* rb, const int32_t* re,
+               const double* x, double* y, int nrhs);
+void cg_init(hipStream_t st, int n, const double* b, const double* Sx, double* r, double* p, double* state,
+             double tol, int nrhs);
+void cg_step(hipStream_t st, int n, double* x, double* r, double* p, const double* q, double* state, double tol,
+             int nrhs);
 
 }  // namespace elmddm

@@ -1605,3 +1605,148 @@ void backsolve_rhs_multi(hipStream_t st, int N, int n, int kpad, const double* X
 }
 
 }  // namespace elmddm
+
+// ---------------------------------------------------------------------------
+// Conjugate gradients on the interface system S u = g (the paper's interface
+// solver, Section 3), on the kept dense S in the envelope order, for nrhs
+// right-hand sides at once.
+// ---------------------------------------------------------------------------
+namespace elmddm {
+
+// up[r][perm[E] mg + i] = u[r][E mg + i]
+__global__ void permute_kernel(int nE, int mg, const int32_t* perm, const double* u, double* up)
+{
+    const long long n = (long long)nE * mg;
+    const long long r = blockIdx.y;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n) return;
+    const int E = idx / mg, i = idx % mg;
+    up[r * n + (long long)perm[E] * mg + i] = u[r * n + idx];
+}
+
+void permute(hipStream_t st, int nE, int mg, const int32_t* perm, const double* u, double* up, int nrhs)
+{
+    if (nE <= 0) return;
+    hipLaunchKernelGGL(permute_kernel, dim3((nE * mg + 255) / 256, nrhs), dim3(256), 0, st, nE, mg, perm, u, up);
+}
+
+// y_r = S x_r for symmetric S (full storage, column-major, ld lds) whose
+// column i is zero outside rows [rb[i/64], re[i/64]): y_r[i] is the dot
+// product of column i with x_r.  One wave per column, lanes along the rows;
+// up to 8 right-hand sides per pass over the column.
+__global__ __launch_bounds__(256) void band_symv_kernel(int n, const double* S, int lds, const int32_t* rb,
+                                                        const int32_t* re, const double* x, double* y,
+                                                        int nrhs)
+{
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= n) return;
+    const int r0 = rb[i / 64], r1 = re[i / 64];
+    const double* col = S + (long long)i * lds;
+    for (int q0 = 0; q0 < nrhs; q0 += 8) {
+        const int nq = nrhs - q0 < 8 ? nrhs - q0 : 8;
+        double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int r = r0 + lane; r < r1; r += 64) {
+            const double s = col[r];
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (q < nq) acc[q] += s * x[(long long)(q0 + q) * n + r];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (q < nq) {
+                const double v = wave_sum(acc[q]);
+                if (lane == 0) y[(long long)(q0 + q) * n + i] = v;
+            }
+    }
+}
+
+void band_symv(hipStream_t st, int n, const double* S, int lds, const int32_t* rb, const int32_t* re,
+               const double* x, double* y, int nrhs)
+{
+    hipLaunchKernelGGL(band_symv_kernel, dim3((n + 3) / 4), dim3(256), 0, st, n, S, lds, rb, re, x, y, nrhs);
+}
+
+__device__ double block_sum(double v, double* red)
+{
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += red[k];
+    return t;
+}
+
+// state[r] = {rr, bb, done, iterations}
+__global__ __launch_bounds__(1024) void cg_init_kernel(int n, const double* b, const double* Sx, double* r,
+                                                       double* p, double* state, double tol)
+{
+    __shared__ double red[16];
+    const long long o = (long long)blockIdx.x * n;
+    double rr = 0.0, bb = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double ri = b[o + i] - Sx[o + i];
+        r[o + i] = ri;
+        p[o + i] = ri;
+        rr += ri * ri;
+        bb += b[o + i] * b[o + i];
+    }
+    rr = block_sum(rr, red);
+    bb = block_sum(bb, red);
+    if (threadIdx.x == 0) {
+        double* s = state + 4 * blockIdx.x;
+        s[0] = rr;
+        s[1] = bb;
+        s[2] = (rr <= tol * tol * bb) ? 1.0 : 0.0;
+        s[3] = 0.0;
+    }
+}
+
+// One CG step for right-hand side blockIdx.x, given q = S p.
+__global__ __launch_bounds__(1024) void cg_step_kernel(int n, double* x, double* r, double* p, const double* q,
+                                                       double* state, double tol)
+{
+    __shared__ double red[16];
+    double* s = state + 4 * blockIdx.x;
+    if (s[2] != 0.0) return;   // converged (uniform over the block)
+    const long long o = (long long)blockIdx.x * n;
+    double pq = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) pq += p[o + i] * q[o + i];
+    pq = block_sum(pq, red);
+    const double rr = s[0];
+    const double alpha = pq > 0.0 ? rr / pq : 0.0;
+    double rr2 = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        x[o + i] += alpha * p[o + i];
+        const double ri = r[o + i] - alpha * q[o + i];
+        r[o + i] = ri;
+        rr2 += ri * ri;
+    }
+    rr2 = block_sum(rr2, red);
+    const bool done = rr2 <= tol * tol * s[1] || !(pq > 0.0);
+    const double beta = rr > 0.0 ? rr2 / rr : 0.0;
+    if (!done)
+        for (int i = threadIdx.x; i < n; i += blockDim.x) p[o + i] = r[o + i] + beta * p[o + i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        s[0] = rr2;
+        s[2] = done ? (pq > 0.0 ? 1.0 : 2.0) : 0.0;
+        s[3] += 1.0;
+    }
+}
+
+void cg_init(hipStream_t st, int n, const double* b, const double* Sx, double* r, double* p, double* state,
+             double tol, int nrhs)
+{
+    hipLaunchKernelGGL(cg_init_kernel, dim3(nrhs), dim3(1024), 0, st, n, b, Sx, r, p, state, tol);
+}
+
+void cg_step(hipStream_t st, int n, double* x, double* r, double* p, const double* q, double* state, double tol,
+             int nrhs)
+{
+    hipLaunchKernelGGL(cg_step_kernel, dim3(nrhs), dim3(1024), 0, st, n, x, r, p, q, state, tol);
+}
+
+}  // namespace elmddm

@@ -17,8 +17,18 @@
 using namespace elmddm;
 
 namespace {
-
 thread_local std::string g_last_error;
+}
+
+namespace elmddm {
+int record_error(int status, const char* msg)
+{
+    g_last_error = msg;
+    return status;
+}
+}  // namespace elmddm
+
+namespace {
 
 elmddm_status fail(elmddm_status st, const std::string& msg)
 {
@@ -82,6 +92,8 @@ struct elmddm_plan {
     int rhs_cap = 0;
     double *Fr = nullptr, *Tm = nullptr, *Hm = nullptr, *Ph = nullptr, *abufR = nullptr;
     double *yR = nullptr, *uR = nullptr, *Vm = nullptr;
+    double *cgX = nullptr, *cgR = nullptr, *cgP = nullptr, *cgQ = nullptr, *cgS = nullptr;
+    int32_t *d_rb = nullptr, *d_re = nullptr;   // row band of each 64-column block of S
     // stage timing
     bool timing = false;
     hipEvent_t ev[ELMDDM_NUM_STAGES + 1] = {};
@@ -801,7 +813,8 @@ elmddm_status elmddm_plan_reserve_rhs(elmddm_plan* P, int32_t max_rhs)
     if (P->B != 1) return fail(ELMDDM_UNSUPPORTED, "further right-hand sides need a plan with batch 1");
     if (max_rhs < 1 || max_rhs > 4096) return fail(ELMDDM_INVALID_ARG, "max_rhs must be in [1, 4096]");
     if (max_rhs <= P->rhs_cap) return ELMDDM_OK;
-    for (double** q : {&P->Fr, &P->Tm, &P->Hm, &P->Ph, &P->abufR, &P->yR, &P->uR, &P->Vm}) {
+    for (double** q : {&P->Fr, &P->Tm, &P->Hm, &P->Ph, &P->abufR, &P->yR, &P->uR, &P->Vm, &P->cgX, &P->cgR,
+                       &P->cgP, &P->cgQ, &P->cgS}) {
         if (*q) {
             P->allocs.erase(std::find(P->allocs.begin(), P->allocs.end(), (void*)*q));
             (void)hipFree(*q);
@@ -819,42 +832,68 @@ elmddm_status elmddm_plan_reserve_rhs(elmddm_plan* P, int32_t max_rhs)
     if ((st = P->dalloc(&P->abufR, R * std::max(P->nE, 1) * P->mg)) != ELMDDM_OK) return st;
     if ((st = P->dalloc(&P->yR, R * nGm)) != ELMDDM_OK) return st;
     if ((st = P->dalloc(&P->uR, R * nGm)) != ELMDDM_OK) return st;
+    for (double** q : {&P->cgX, &P->cgR, &P->cgP, &P->cgQ})
+        if ((st = P->dalloc(q, R * nGm)) != ELMDDM_OK) return st;
+    if ((st = P->dalloc(&P->cgS, 4 * R)) != ELMDDM_OK) return st;
+    if (!P->d_rb && P->nblkS > 0) {
+        if ((st = P->upload(&P->d_rb, P->kbeg)) != ELMDDM_OK) return st;
+        if ((st = P->upload(&P->d_re, P->rend)) != ELMDDM_OK) return st;
+    }
     P->rhs_cap = max_rhs;
     return ELMDDM_OK;
 }
 
-elmddm_status elmddm_solve_rhs(elmddm_plan* P, int32_t nrhs, const double* f, const double* g,
-                               double* u_gamma, double* c, void* stream)
+namespace {
+
+elmddm_status rhs_checks(elmddm_plan* P, int32_t nrhs, const void* f)
 {
     if (!P) return fail(ELMDDM_INVALID_ARG, "NULL plan");
     if (P->B != 1) return fail(ELMDDM_UNSUPPORTED, "further right-hand sides need a plan with batch 1");
-    if (nrhs < 0 || !f) return fail(ELMDDM_INVALID_ARG, "bad nrhs or NULL f");
-    if (P->nG > 0 && !u_gamma) return fail(ELMDDM_INVALID_ARG, "u_gamma is NULL");
+    if (nrhs < 0 || !f) return fail(ELMDDM_INVALID_ARG, "bad nrhs or NULL input");
     if (!P->factors_valid) return fail(ELMDDM_INVALID_ARG, "no factors: call elmddm_solve on this plan first");
     if (P->rhs_cap < 1) return fail(ELMDDM_INVALID_ARG, "call elmddm_plan_reserve_rhs first");
-    hipStream_t st = (hipStream_t)stream;
+    return ELMDDM_OK;
+}
+
+// For R sources starting at f (g may be NULL): Hm = h = Q^T F per subdomain
+// and, if the problem has an interface, the Schur right-hand side of eq.
+// schur in the envelope order in yR.
+void rhs_stage(elmddm_plan* P, hipStream_t st, int R, const double* f, const double* g)
+{
     const int N = P->N, n = P->n, ldx = P->ldx, ldg = P->ldg, ldf = P->gram_rows, nG = P->nG;
     const int ldp = P->ldp, mg = P->mg, kp = P->kpad;
     const long long nf = (long long)N * P->q2;
     // after a solve: X0 = Q2 (all rows), X1 rows [mI, ldx) = Q3 interface rows, h row, Z^T rows
-    const double* Q2 = P->X0;
-    const double* X1 = P->X1;
+    rhs_assemble(st, row_table(P), ldx, P->gram_rows, ldf, f, g, N, R, nf, P->nB, P->Fr);
+    // h = L3^{-1} Q2^T F
+    gemm_f64(st, true, false, 0, false, n, R, P->gram_rows, 1.0, P->X0, ldx, P->sX, P->Fr, ldf, (long long)R * ldf,
+             0.0, P->Tm, n, (long long)R * n, N);
+    gemm_f64(st, false, false, 0, false, n, R, n, 1.0, P->Linv[2], ldg, P->sL, P->Tm, n, (long long)R * n, 0.0,
+             P->Hm, n, (long long)R * n, N);
+    if (nG == 0) return;
+    // [q; a] = [Q_Gamma^T h; Z h] per subdomain, laid out [rhs][subdomain][ldp]
+    gemm_f64(st, false, false, 0, false, 2 * kp + 16, R, n, 1.0, P->X1 + P->mI, ldx, P->sX, P->Hm, n,
+             (long long)R * n, 0.0, P->Ph, N * ldp, ldp, N);
+    schur_avec(st, P->nE, P->d_adesc, P->Ph, ldp, ldp, kp + 16, 0, mg, P->abufR, N, R);
+    schur_rhs(st, P->nE, mg, P->d_qdesc, P->d_gptr, P->d_gdesc, P->Ph, ldp, ldp, 0, P->Mbuf, P->abufR, P->yR, 1,
+              P->d_perm, N, 0, (long long)P->nE * mg, nG, R);
+}
+
+}  // namespace
+
+elmddm_status elmddm_solve_rhs(elmddm_plan* P, int32_t nrhs, const double* f, const double* g,
+                               double* u_gamma, double* c, void* stream)
+{
+    elmddm_status est = rhs_checks(P, nrhs, f);
+    if (est != ELMDDM_OK) return est;
+    if (P->nG > 0 && !u_gamma) return fail(ELMDDM_INVALID_ARG, "u_gamma is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    const int N = P->N, n = P->n, ldx = P->ldx, ldg = P->ldg, nG = P->nG, mg = P->mg, kp = P->kpad;
+    const long long nf = (long long)N * P->q2;
     for (int r0 = 0; r0 < nrhs; r0 += P->rhs_cap) {
         const int R = std::min(P->rhs_cap, nrhs - r0);
-        rhs_assemble(st, row_table(P), ldx, P->gram_rows, ldf, f + r0 * nf, g ? g + r0 * P->nB : nullptr, N, R,
-                     nf, P->nB, P->Fr);
-        // h = L3^{-1} Q2^T F
-        gemm_f64(st, true, false, 0, false, n, R, P->gram_rows, 1.0, Q2, ldx, P->sX, P->Fr, ldf,
-                 (long long)R * ldf, 0.0, P->Tm, n, (long long)R * n, N);
-        gemm_f64(st, false, false, 0, false, n, R, n, 1.0, P->Linv[2], ldg, P->sL, P->Tm, n, (long long)R * n,
-                 0.0, P->Hm, n, (long long)R * n, N);
+        rhs_stage(P, st, R, f + r0 * nf, g ? g + r0 * P->nB : nullptr);
         if (nG > 0) {
-            // [q; a] = [Q_Gamma^T h; Z h] per subdomain, laid out [rhs][subdomain][ldp]
-            gemm_f64(st, false, false, 0, false, 2 * kp + 16, R, n, 1.0, X1 + P->mI, ldx, P->sX, P->Hm, n,
-                     (long long)R * n, 0.0, P->Ph, N * ldp, ldp, N);
-            schur_avec(st, P->nE, P->d_adesc, P->Ph, ldp, ldp, kp + 16, 0, mg, P->abufR, N, R);
-            schur_rhs(st, P->nE, mg, P->d_qdesc, P->d_gptr, P->d_gdesc, P->Ph, ldp, ldp, 0, P->Mbuf, P->abufR,
-                      P->yR, 1, P->d_perm, N, 0, (long long)P->nE * mg, nG, R);
             // L y = g, then L^T u = y, with the envelope factor of S
             const int BR = 4 * NB;
             for (int j0 = 0; j0 < nG; j0 += BR) {
@@ -871,7 +910,7 @@ elmddm_status elmddm_solve_rhs(elmddm_plan* P, int32_t nrhs, const double* f, co
         }
         if (c) {
             // c = Linv1^T Linv2^T Linv3^T (h + Q_Gamma^T u)
-            backsolve_rhs_multi(st, N, n, kp, X1, ldx, P->sX, P->mI, P->d_gidx,
+            backsolve_rhs_multi(st, N, n, kp, P->X1, ldx, P->sX, P->mI, P->d_gidx,
                                 nG > 0 ? u_gamma + (long long)r0 * nG : nullptr, nG, P->Hm, P->Vm, R);
             gemm_f64(st, true, false, 0, false, n, R, n, 1.0, P->Linv[2], ldg, P->sL, P->Vm, n, (long long)R * n,
                      0.0, P->Tm, n, (long long)R * n, N);
@@ -882,6 +921,70 @@ elmddm_status elmddm_solve_rhs(elmddm_plan* P, int32_t nrhs, const double* f, co
         }
     }
     return check_launch("solve_rhs");
+}
+
+elmddm_status elmddm_schur_rhs(elmddm_plan* P, int32_t nrhs, const double* f, const double* g, double* rhs,
+                               void* stream)
+{
+    elmddm_status est = rhs_checks(P, nrhs, f);
+    if (est != ELMDDM_OK) return est;
+    if (P->nG > 0 && !rhs) return fail(ELMDDM_INVALID_ARG, "rhs is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    const long long nf = (long long)P->N * P->q2;
+    for (int r0 = 0; r0 < nrhs && P->nG > 0; r0 += P->rhs_cap) {
+        const int R = std::min(P->rhs_cap, nrhs - r0);
+        rhs_stage(P, st, R, f + r0 * nf, g ? g + r0 * P->nB : nullptr);
+        unpermute(st, P->nE, P->mg, P->d_perm, P->yR, rhs + (long long)r0 * P->nG, R);
+    }
+    return check_launch("schur_rhs");
+}
+
+elmddm_status elmddm_interface_cg(elmddm_plan* P, int32_t nrhs, const double* rhs, double* u, double tol,
+                                  int32_t maxit, int32_t* iters, double* relres, void* stream)
+{
+    if (!P) return fail(ELMDDM_INVALID_ARG, "NULL plan");
+    if (nrhs < 0 || (P->nG > 0 && (!rhs || !u))) return fail(ELMDDM_INVALID_ARG, "bad nrhs or NULL vector");
+    if (!(tol > 0.0) || maxit < 0) return fail(ELMDDM_INVALID_ARG, "tol must be > 0 and maxit >= 0");
+    if (P->B != 1) return fail(ELMDDM_UNSUPPORTED, "interface CG needs a plan with batch 1");
+    if (!P->schur_valid) return fail(ELMDDM_INVALID_ARG, "no kept Schur matrix (elmddm_plan_keep_schur before the solve)");
+    if (P->rhs_cap < 1) return fail(ELMDDM_INVALID_ARG, "call elmddm_plan_reserve_rhs first");
+    hipStream_t st = (hipStream_t)stream;
+    const int nG = P->nG, mg = P->mg;
+    bool all_done = true;
+    std::vector<double> state;
+    for (int r0 = 0; r0 < nrhs && nG > 0; r0 += P->rhs_cap) {
+        const int R = std::min(P->rhs_cap, nrhs - r0);
+        permute(st, P->nE, mg, P->d_perm, rhs + (long long)r0 * nG, P->yR, R);
+        permute(st, P->nE, mg, P->d_perm, u + (long long)r0 * nG, P->cgX, R);
+        band_symv(st, nG, P->Skeep, P->lds, P->d_rb, P->d_re, P->cgX, P->cgQ, R);
+        cg_init(st, nG, P->yR, P->cgQ, P->cgR, P->cgP, P->cgS, tol, R);
+        state.assign(4 * R, 0.0);
+        for (int it = 0; it < maxit; ++it) {
+            band_symv(st, nG, P->Skeep, P->lds, P->d_rb, P->d_re, P->cgP, P->cgQ, R);
+            cg_step(st, nG, P->cgX, P->cgR, P->cgP, P->cgQ, P->cgS, tol, R);
+            if ((it & 15) == 15 || it + 1 == maxit) {
+                if (hipMemcpyAsync(state.data(), P->cgS, 4 * R * sizeof(double), hipMemcpyDeviceToHost, st) !=
+                        hipSuccess || hipStreamSynchronize(st) != hipSuccess)
+                    return check_launch("interface_cg poll");
+                bool done = true;
+                for (int q = 0; q < R; ++q) done = done && state[4 * q + 2] != 0.0;
+                if (done) break;
+            }
+        }
+        if (hipMemcpyAsync(state.data(), P->cgS, 4 * R * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return check_launch("interface_cg state");
+        for (int q = 0; q < R; ++q) {
+            if (iters) iters[r0 + q] = (int32_t)state[4 * q + 3];
+            if (relres) relres[r0 + q] = state[4 * q + 1] > 0.0 ? std::sqrt(state[4 * q] / state[4 * q + 1]) : 0.0;
+            all_done = all_done && state[4 * q + 2] == 1.0;
+        }
+        unpermute(st, P->nE, mg, P->d_perm, P->cgX, u + (long long)r0 * nG, R);
+    }
+    elmddm_status est = check_launch("interface_cg");
+    if (est != ELMDDM_OK) return est;
+    if (!all_done) return fail(ELMDDM_NOT_CONVERGED, "interface CG did not reach the tolerance");
+    return ELMDDM_OK;
 }
 
 elmddm_status elmddm_autotune(elmddm_plan* P, void* stream, int32_t* choice)

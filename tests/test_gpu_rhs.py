@@ -99,3 +99,51 @@ def test_further_rhs_need_factors_and_batch_one(gpu):
     with pytest.raises(B.ElmddmError) as e:
         pb.reserve_rhs(1)
     assert e.value.status == B.UNSUPPORTED
+
+
+def test_schur_rhs_and_interface_cg_match_oracle_and_direct_solve(gpu):
+    """The Schur right-hand side of a new source equals the oracle's g, and
+    CG on the kept S (the paper's interface solver) converges to the direct
+    solution."""
+    import torch
+    from oracle import ddm
+    from oracle.layout import build_layout
+    from paper_2406_15959_amd import binding as B
+    P = wl.Problem(3, 3, 60, 10, 10, 8, 6, R=2.0)
+    dev = torch.device("cuda:0")
+    plan = B.Plan(to_c_problem(P))
+    plan.keep_schur(True)
+    g0 = gpu_solve(P, 21, plan=plan)
+    assert g0["info"].status == 0
+    s = plan.sizes
+    alphas = wl.fourier_coeffs(5, modes=6, count=3)
+    ipts = plan.points(B.POINTS_INTERIOR)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+    f = t(wl.fourier_source(alphas, ipts[:, 0], ipts[:, 1]))
+    plan.reserve_rhs(2)
+    nG = s.n_interface
+    rhs = torch.zeros(3 * nG, dtype=torch.float64, device=dev)
+    plan.schur_rhs(3, f, None, rhs)
+    u_direct = torch.zeros(3 * nG, dtype=torch.float64, device=dev)
+    plan.solve_rhs(3, f, None, u_direct)
+    u_cg = torch.zeros(3 * nG, dtype=torch.float64, device=dev)
+    st, its = plan.interface_cg(3, rhs, u_cg, 1e-13, 5000)
+    assert st == B.OK and all(0 < k < 5000 for k in its), its
+    lay = build_layout(P)
+    W, b = wl.hidden_params(P, 21)
+    zero = lambda prob, x, y: np.zeros_like(np.asarray(x, dtype=np.float64))
+    for r in range(3):
+        src = lambda prob, x, y, r=r: wl.fourier_source(alphas[r:r + 1], x, y)[0]
+        sol = ddm.solve(P, W, b, ddm.problem_data(P, lay, src, zero, wl.coefficient), lay)
+        got_rhs = rhs[r * nG:(r + 1) * nG].cpu().numpy()
+        assert rel(got_rhs, sol.g) <= 1e-9
+        ud = u_direct[r * nG:(r + 1) * nG].cpu().numpy()
+        uc = u_cg[r * nG:(r + 1) * nG].cpu().numpy()
+        assert rel(uc, ud) <= 1e-9
+        assert rel(ud, sol.u_gamma) <= TOL_FP64
+    # a converged start needs no iteration; maxit 0 leaves the guess untouched
+    st, its = plan.interface_cg(1, rhs, u_cg, 1e-6, 100)
+    assert st == B.OK and its == [0]
+    u0 = torch.zeros(nG, dtype=torch.float64, device=dev)
+    st, its = plan.interface_cg(1, rhs, u0, 1e-13, 0)
+    assert st == B.NOT_CONVERGED and its == [0] and float(u0.abs().max()) == 0.0

@@ -234,3 +234,25 @@ def fourier_exact(alpha, x, y):
     M = np.asarray(alpha).shape[-1]
     _, w = _modes(M)
     return fourier_series_at(alpha, x, y, scale=1.0 / (math.pi ** 2 * (w - 1.0)))
+
+
+# ---------------------------------------------------------------------------
+# Initial weights of the interface-predicting MLP (random numbers only).
+# ---------------------------------------------------------------------------
+
+def mlp_dims(in_dim: int, out_dim: int, hidden: int = 512):
+    """Layer widths (in, hidden, hidden, out)."""
+    return (in_dim, hidden, hidden, out_dim)
+
+
+def mlp_init(dims, seed: int):
+    """Flat float32 parameter vector: for each layer (fan_in -> fan_out) its
+    weight matrix (fan_out x fan_in, column-major), then its bias, all
+    i.i.d. U[-1/sqrt(fan_in), 1/sqrt(fan_in)]."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fi, fo in zip(dims[:-1], dims[1:]):
+        lim = 1.0 / math.sqrt(fi)
+        parts.append(rng.uniform(-lim, lim, fo * fi))
+        parts.append(rng.uniform(-lim, lim, fo))
+    return np.concatenate(parts).astype(np.float32)
