@@ -53,12 +53,134 @@ def measured_traffic(gram_code, batch):
         return None
 
 
+def learned_leg(B, wl, torch, log):
+    """Learned interface warm start on the 16x16 Fourier-source workload:
+    one fixed hidden layer, sources differ.  Measures full solves (FP64 and
+    mixed), exact per-source solves with cached factors, MLP training on
+    4096 method-generated pairs, and on 512 held-out sources the learned
+    path (prediction + residual check, exact solve as fallback) and the
+    paper's CG from a zero vs. a learned start."""
+    from paper_2406_15959_amd import learned
+    P = wl.CONFIG_16x16
+    M, ntrain, ntest, ncg = 32, 4096, 512, 16
+    dev = torch.device("cuda:0")
+    cp = B.make_problem(P.x0, P.x1, P.y0, P.y1, P.nsub_x, P.nsub_y, P.neurons, P.q_x, P.q_y,
+                        P.m_bdry_edge, P.m_ifc_edge, P.op)
+    plan = B.Plan(cp)
+    plan.keep_schur(True)
+    plan.autotune()
+    s = plan.sizes
+    nG = s.n_interface
+    ipts = plan.points(B.POINTS_INTERIOR)
+    bpts = plan.points(B.POINTS_BOUNDARY)
+    t = lambda a, dt=torch.float64: torch.from_numpy(np.ascontiguousarray(a)).to(dev, dt)
+    W, b = wl.hidden_params(P, 4000)
+    f0, g0, _ = wl.sample_data(P, ipts, bpts)
+    dW, db, df0, dg0 = t(W), t(b), t(f0), t(g0)
+    du = torch.zeros(nG, dtype=torch.float64, device=dev)
+    dc = torch.zeros(s.nsub * s.neurons, dtype=torch.float64, device=dev)
+    out = {"workload": "2D Poisson 16x16 subdomains, 400 tanh neurons (U[-4,4]), 40x40 interior points, "
+                       "40 points per edge; sources: random sine series, 32 modes per axis",
+           "interface_unknowns": nG}
+    full = {}
+    for name, mode in (("mixed", B.MODE_MIXED), ("fp64", B.MODE_FP64)):
+        plan.set_mode(mode)
+        plan.solve(dW, db, df0, dg0, None, du, dc)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            plan.solve(dW, db, df0, dg0, None, du, dc)
+        torch.cuda.synchronize()
+        full[name] = {"solves_per_s": 3 / (time.perf_counter() - t0), "status": plan.solve_info().status}
+    out["full_solves"] = full
+    log("learned leg: full solves done")
+    plan.reserve_rhs(64)
+    a_train = wl.fourier_coeffs(4100, modes=M, count=ntrain)
+    a_test = wl.fourier_coeffs(100000, modes=M, count=ntest)
+    U_train = torch.empty(ntrain, nG, dtype=torch.float64, device=dev)
+    U_test = torch.empty(ntest, nG, dtype=torch.float64, device=dev)
+    for r0 in range(0, ntrain, 256):
+        f = t(wl.fourier_source(a_train[r0:r0 + 256], ipts[:, 0], ipts[:, 1]))
+        U_train[r0:r0 + 256] = learned.generate_pairs(plan, f, f.shape[0])
+    f_test = t(wl.fourier_source(a_test, ipts[:, 0], ipts[:, 1]))
+    torch.cuda.synchronize()
+    # exact per-source solves with cached factors (u_Gamma and every c_s)
+    c_test = torch.empty(ntest * s.nsub * s.neurons, dtype=torch.float64, device=dev)
+    u_test = torch.empty(ntest * nG, dtype=torch.float64, device=dev)
+    t0 = time.perf_counter()
+    plan.solve_rhs(ntest, f_test, None, u_test, c_test)
+    torch.cuda.synchronize()
+    exact_rate = ntest / (time.perf_counter() - t0)
+    U_test.copy_(u_test.view(ntest, nG))
+    log("learned leg: pairs generated")
+    X_train = t(wl.fourier_inputs(a_train), torch.float32)
+    X_test = t(wl.fourier_inputs(a_test), torch.float32)
+    net = B.MLP(M * M, 512, nG, max_batch=256)
+    net.set_params(t(wl.mlp_init(net.dims, 4001), torch.float32))
+    steps, batch = 3200, 256
+    rng = np.random.default_rng(4002)
+    order = np.concatenate([rng.permutation(ntrain) for _ in range(steps * batch // ntrain + 1)])
+    losses = torch.zeros(steps, dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    scale = learned.train(net, X_train, U_train, steps, batch, 1e-3,
+                          t(order[:steps * batch].astype(np.int32), torch.int32), losses)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    log("learned leg: trained")
+    # learned path: prediction, residual check, exact solve as fallback
+    tau = 1e-9
+    rhs = torch.empty(ntest * nG, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pred = learned.predict(net, X_test, scale)
+    plan.schur_rhs(ntest, f_test, None, rhs)
+    res = learned.residuals(plan, rhs.view(ntest, nG), pred)
+    rejected = [i for i in range(ntest) if res[i] > tau]
+    if rejected:
+        idx = torch.tensor(rejected, device=dev)
+        fr = f_test.view(ntest, -1)[idx].contiguous()
+        ur = torch.empty(len(rejected) * nG, dtype=torch.float64, device=dev)
+        cr = torch.empty(len(rejected) * s.nsub * s.neurons, dtype=torch.float64, device=dev)
+        plan.solve_rhs(len(rejected), fr, None, ur, cr)
+    torch.cuda.synchronize()
+    learned_rate = ntest / (time.perf_counter() - t0)
+    err = ((pred - U_test).norm(dim=1) / U_test.norm(dim=1)).cpu().numpy()
+    # the paper's interface solver, CG, from a zero and from a learned start
+    cg = {}
+    tol = 1e-11
+    rhs_cg = rhs.view(ntest, nG)[:ncg].contiguous()
+    for name, guess in (("zero_start", torch.zeros_like(rhs_cg)), ("learned_start", pred[:ncg].contiguous())):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u, its, _, st = learned.solve_with_guess(plan, rhs_cg, guess, tol, 40000)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        e = ((u - U_test[:ncg]).norm(dim=1) / U_test[:ncg].norm(dim=1)).max().item()
+        cg[name] = {"iterations_mean": float(np.mean(its)), "interface_solves_per_s": ncg / el,
+                    "status": int(st), "max_rel_l2_vs_exact": e}
+    cg["saving"] = 1.0 - cg["learned_start"]["iterations_mean"] / cg["zero_start"]["iterations_mean"]
+    log("learned leg: CG done")
+    out.update({
+        "exact_per_source_solves_per_s": exact_rate,
+        "learned_per_source_solves_per_s": learned_rate,
+        "learned_direct_accept_rate": 1.0 - len(rejected) / ntest,
+        "accept_tau": tau,
+        "prediction_rel_l2_median": float(np.median(err)), "prediction_rel_l2_max": float(err.max()),
+        "mlp": {"dims": list(net.dims), "train_pairs": ntrain, "steps": steps, "batch": batch,
+                "train_seconds": train_s, "final_loss": float(losses[-20:].mean().item())},
+        "cg_tol": tol, "cg_systems": ncg, "cg": cg,
+    })
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the 16x16 learned warm-start leg")
     ap.add_argument("--batch", type=int, default=8, help="problem instances solved together per step")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration) and exit")
@@ -204,6 +326,11 @@ def main():
                              "achieved": flops_per_launch / (gram32_ms * 1e-3) / 1e12 if gram32_ms > 0 else 0.0,
                              "peak": MFMA_F32_PEAK_TFLOPS, "unit": "TFLOP/s", "avg_launch_ms": gram32_ms}}
     roofline["f32_gram"]["frac"] = roofline["f32_gram"]["achieved"] / MFMA_F32_PEAK_TFLOPS
+    learned_out = None
+    if not args.no_learned:
+        del plan, inst, df, dg, du, dc
+        torch.cuda.empty_cache()
+        learned_out = learned_leg(B, wl, torch, lambda m: print(m, file=sys.stderr, flush=True))
     best = modes["mixed"]
     out = {
         "metric": "ELM-DDM solves/sec at fixed rel-L2 vs FP64 oracle: mixed+learned vs plain FP64",
@@ -228,6 +355,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "modes": modes,
+        "learned": learned_out,
     }
     print(json.dumps(out), flush=True)
 

@@ -38,3 +38,11 @@ def test_fourier_features_are_standardised():
     assert abs(np.mean(z**2) - 1.0) < 0.02
     # row-major: feature k1 * M + k2 holds mode (k1 + 1, k2 + 1)
     assert np.isclose(z[0, 1 * 32 + 2], a[0, 1, 2] * math.sqrt(1 + 4 + 9))
+
+
+def test_fourier_inputs_have_unit_mean_square():
+    a = wl.fourier_coeffs(6, modes=32, count=256)
+    z = wl.fourier_inputs(a)
+    assert z.shape == (256, 1024)
+    assert abs(np.mean(z**2) - 1.0) < 0.03
+    assert np.allclose(z[3] / a[3].ravel(), z[3, 0] / a[3, 0, 0])
