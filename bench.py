@@ -226,6 +226,7 @@ def main():
     dc = torch.zeros(nb * s.nsub * s.neurons, dtype=torch.float64, device=dev)
 
     tuned = plan.autotune()
+    tune_report = {str(k): [round(v[0], 4), round(v[1], 4)] for k, v in plan.autotune_times().items()}
     ex, ey = wl.eval_grid(P)
     xy = t(np.stack([ex, ey], 1))
     uh = torch.zeros(len(ex), dtype=torch.float64, device=dev)
@@ -351,7 +352,8 @@ def main():
         "config": {"workload": "2D Poisson 8x8 subdomains, 400 tanh neurons each (U[-4,4]), "
                                "40x40 interior points, 40 points per boundary/interface edge",
                    "subdomains": P.nsub, "neurons": n, "interface_unknowns": s.n_interface,
-                   "instances_per_step": nb, "autotuned_kernels": tuned},
+                   "instances_per_step": nb, "autotuned_kernels": tuned,
+                   "autotune_ms_gram_trsm": tune_report},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "modes": modes,

@@ -250,6 +250,12 @@ elmddm_status elmddm_plan_set_mode(elmddm_plan* plan, int32_t mode);
  * strip width T. */
 elmddm_status elmddm_autotune(elmddm_plan* plan, void* stream, int32_t* choice);
 
+/* Candidate timings of the last elmddm_autotune (zeros before one): codes
+ * [9] receives the kernel codes, gram_ms [9] and trsm_ms [9] the time of
+ * one Gram product and one triangular solve over the whole batch with each
+ * (host arrays). */
+elmddm_status elmddm_autotune_times(const elmddm_plan* plan, int32_t* codes, double* gram_ms, double* trsm_ms);
+
 /* Per-stage device timing of solves (HIP events recorded on the solve's
  * stream around each stage).  When enabled, every elmddm_solve adds the
  * elapsed time of each stage to running totals; elmddm_stage_times

@@ -35,7 +35,7 @@ EXPORTED = [
     "elmddm_plan_create", "elmddm_plan_create_batch", "elmddm_plan_destroy", "elmddm_plan_sizes", "elmddm_points",
     "elmddm_solve", "elmddm_solve_info", "elmddm_eval", "elmddm_assemble",
     "elmddm_plan_keep_schur", "elmddm_get_schur", "elmddm_set_timing", "elmddm_stage_times", "elmddm_pass_times",
-    "elmddm_autotune", "elmddm_plan_set_mode", "elmddm_plan_reserve_rhs", "elmddm_solve_rhs",
+    "elmddm_autotune", "elmddm_autotune_times", "elmddm_plan_set_mode", "elmddm_plan_reserve_rhs", "elmddm_solve_rhs",
     "elmddm_schur_rhs", "elmddm_interface_cg",
     "elmddm_mlp_create", "elmddm_mlp_destroy", "elmddm_mlp_num_params", "elmddm_mlp_set_params",
     "elmddm_mlp_get_params", "elmddm_mlp_forward", "elmddm_mlp_loss_grad", "elmddm_mlp_adam_step",
@@ -98,6 +98,8 @@ def lib():
         L.elmddm_set_timing.argtypes = [vp, i32]
         L.elmddm_autotune.argtypes = [vp, vp, ctypes.POINTER(i32)]
         L.elmddm_plan_set_mode.argtypes = [vp, i32]
+        L.elmddm_autotune_times.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double),
+                                            ctypes.POINTER(ctypes.c_double)]
         L.elmddm_plan_reserve_rhs.argtypes = [vp, i32]
         L.elmddm_solve_rhs.argtypes = [vp, i32, dp, dp, dp, dp, vp]
         L.elmddm_schur_rhs.argtypes = [vp, i32, dp, dp, dp, vp]
@@ -241,6 +243,14 @@ class Plan:
         ch = (ctypes.c_int32 * 2)()
         _check(lib().elmddm_autotune(self._h, _stream(), ch))
         return list(ch)
+
+    def autotune_times(self):
+        """{code: (gram ms, trsm ms)} of the last autotune."""
+        c = (ctypes.c_int32 * 9)()
+        g = (ctypes.c_double * 9)()
+        t = (ctypes.c_double * 9)()
+        _check(lib().elmddm_autotune_times(self._h, c, g, t))
+        return {c[i]: (g[i], t[i]) for i in range(9)}
 
     def set_timing(self, enable=True):
         _check(lib().elmddm_set_timing(self._h, 1 if enable else 0))

@@ -5,6 +5,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "internal.h"
 
 namespace elmddm {
@@ -133,14 +135,15 @@ __device__ __forceinline__ bool aligned16(const double* p)
 // FP32 accumulation; operands rounded to FP32 when they are staged in LDS,
 // result widened to FP64 on store).  The FP32 accumulator's element r of lane
 // l is D[4*(l/16) + r][l%16].  LDS rows are padded so that the four k rows a
-// wave reads at once fall in different banks.
+// wave reads at once fall in different banks (for FP64: the two 16-lane
+// groups of each half-wave).
 template <class CT, bool TA, bool TB, int KMODE, bool LOWER, int GB_K, bool XCD>
 __global__ __launch_bounds__(256) void gemm_mfma_kernel(
     int M, int N, int K, double alpha, const double* A, int lda, long long sA, const double* B,
     int ldb, long long sB, double beta, double* C, int ldc, long long sC)
 {
     constexpr bool F64 = sizeof(CT) == 8;
-    constexpr int PAD = F64 ? 0 : 16;
+    constexpr int PAD = 16;
     typedef CT acc_t __attribute__((ext_vector_type(4)));
     const unsigned gx = gridDim.x, gy = gridDim.y;
     const unsigned total = gx * gy * gridDim.z;
@@ -229,33 +232,76 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(
         }
     };
 
+    // 16 x 16 blocks of this wave that carry work: bit 2u + v for block (u, v).
+    // Blocks outside M x N, and in lower mode blocks strictly above the
+    // diagonal, are skipped; with KMODE 1/2 a block also drops out of the K
+    // stages where op(B) is zero for its columns.  The mask selects a
+    // branch-free MFMA sequence once per stage.
+    const int lr = lane & 15, lk = lane >> 4;
+    int wmask = 0;
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            const int R0 = m0 + wm * 32 + u * 16, C0 = n0 + wn * 32 + v * 16;
+            if (R0 < M && C0 < N && (!LOWER || R0 + 15 >= C0)) wmask |= 1 << (2 * u + v);
+        }
+    auto mma = [](CT a, CT b, acc_t c) {
+        if constexpr (F64) return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+        else return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    };
+    auto stage = [&](auto mc) {
+        constexpr int MK = decltype(mc)::value;
+        CT av[GB_K / 4][2], bv[GB_K / 4][2];
+#pragma unroll
+        for (int ks = 0; ks < GB_K / 4; ++ks) {
+            const int k = ks * 4 + lk;
+            if constexpr ((MK & 3) != 0) av[ks][0] = As[k][wm * 32 + lr];
+            if constexpr ((MK & 12) != 0) av[ks][1] = As[k][wm * 32 + 16 + lr];
+            if constexpr ((MK & 5) != 0) bv[ks][0] = Bs[k][wn * 32 + lr];
+            if constexpr ((MK & 10) != 0) bv[ks][1] = Bs[k][wn * 32 + 16 + lr];
+        }
+#pragma unroll
+        for (int ks = 0; ks < GB_K / 4; ++ks) {
+            if constexpr ((MK & 1) != 0) acc[0][0] = mma(av[ks][0], bv[ks][0], acc[0][0]);
+            if constexpr ((MK & 2) != 0) acc[0][1] = mma(av[ks][0], bv[ks][1], acc[0][1]);
+            if constexpr ((MK & 4) != 0) acc[1][0] = mma(av[ks][1], bv[ks][0], acc[1][0]);
+            if constexpr ((MK & 8) != 0) acc[1][1] = mma(av[ks][1], bv[ks][1], acc[1][1]);
+        }
+    };
     const int nk = (kend > kbeg) ? (kend - kbeg + GB_K - 1) / GB_K : 0;
     if (nk > 0) {
         load(kbeg);
         store();
         __syncthreads();
-        const int lr = lane & 15, lk = lane >> 4;
         for (int it = 0; it < nk; ++it) {
-            if (it + 1 < nk) load(kbeg + (it + 1) * GB_K);
-            CT av[GB_K / 4][2], bv[GB_K / 4][2];
+            const int k0 = kbeg + it * GB_K;
+            if (it + 1 < nk) load(k0 + GB_K);
+            int mk = wmask;
 #pragma unroll
-            for (int ks = 0; ks < GB_K / 4; ++ks) {
-                const int k = ks * 4 + lk;
-                av[ks][0] = As[k][wm * 32 + lr];
-                av[ks][1] = As[k][wm * 32 + 16 + lr];
-                bv[ks][0] = Bs[k][wn * 32 + lr];
-                bv[ks][1] = Bs[k][wn * 32 + 16 + lr];
+            for (int v = 0; v < 2; ++v) {
+                const int C0 = n0 + wn * 32 + v * 16;
+                const bool dead = (KMODE == 2 && k0 >= C0 + 16) || (KMODE == 1 && k0 + GB_K <= C0);
+                if (dead) mk &= ~((1 << v) | (1 << (2 + v)));
             }
-#pragma unroll
-            for (int ks = 0; ks < GB_K / 4; ++ks)
-#pragma unroll
-                for (int u = 0; u < 2; ++u)
-#pragma unroll
-                    for (int v = 0; v < 2; ++v)
-                        if constexpr (F64)
-                            acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks][u], bv[ks][v], acc[u][v], 0, 0, 0);
-                        else
-                            acc[u][v] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ks][u], bv[ks][v], acc[u][v], 0, 0, 0);
+            switch (mk) {
+                case 1: stage(std::integral_constant<int, 1>{}); break;
+                case 2: stage(std::integral_constant<int, 2>{}); break;
+                case 3: stage(std::integral_constant<int, 3>{}); break;
+                case 4: stage(std::integral_constant<int, 4>{}); break;
+                case 5: stage(std::integral_constant<int, 5>{}); break;
+                case 6: stage(std::integral_constant<int, 6>{}); break;
+                case 7: stage(std::integral_constant<int, 7>{}); break;
+                case 8: stage(std::integral_constant<int, 8>{}); break;
+                case 9: stage(std::integral_constant<int, 9>{}); break;
+                case 10: stage(std::integral_constant<int, 10>{}); break;
+                case 11: stage(std::integral_constant<int, 11>{}); break;
+                case 12: stage(std::integral_constant<int, 12>{}); break;
+                case 13: stage(std::integral_constant<int, 13>{}); break;
+                case 14: stage(std::integral_constant<int, 14>{}); break;
+                case 15: stage(std::integral_constant<int, 15>{}); break;
+                default: break;
+            }
             __syncthreads();
             if (it + 1 < nk) {
                 store();
@@ -263,13 +309,14 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(
             }
         }
     }
-    const int lr = lane & 15, lq = lane >> 4;
+    const int lq = lane >> 4;
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
+                if (!(wmask & (1 << (2 * bi + bj)))) continue;
                 const int row = m0 + wm * 32 + bi * 16 + (F64 ? r * 4 + lq : lq * 4 + r);
                 const int col = n0 + wn * 32 + bj * 16 + lr;
                 if (row < M && col < N) {
@@ -367,13 +414,20 @@ __global__ __launch_bounds__(64 * T) void gemm_strip_kernel(
     if (KMODE == 1) kbeg = n0 < K ? n0 : K;
     if (KMODE == 2) kend = (n0 + BT) < K ? (n0 + BT) : K;
 
-    __shared__ double As[16][BT];
-    __shared__ double Bs[16][BT];
+    // rows padded so that the two 16-lane groups of a half-wave read
+    // disjoint LDS banks
+    constexpr int SPAD = (BT % 32 == 0) ? 16 : 0;
+    __shared__ double As[16][BT + SPAD];
+    __shared__ double Bs[16][BT + SPAD];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int w = tid >> 6;
     const int lr = lane & 15, lk = lane >> 4;
-    const int jmax = (LOWER && tm == tn) ? w : T - 1;   // wave-uniform
+    // live 16-column blocks of this wave's strip: j in [jlo, jhi).  jhi drops
+    // blocks beyond N or (lower mode, diagonal tile) above the diagonal; with
+    // KMODE 2 the blocks whose columns precede the K stage die (jlo).
+    int jhi = (m0 + 16 * w < M) ? min(T, (N - n0 + 15) / 16) : 0;
+    if (LOWER && tm == tn) jhi = min(jhi, w + 1);
 
     v4d acc[T];
 #pragma unroll
@@ -429,10 +483,28 @@ __global__ __launch_bounds__(64 * T) void gemm_strip_kernel(
         load(kbeg);
         store();
         __syncthreads();
-        for (int it = 0; it < nk; ++it) {
-            if (it + 1 < nk) load(kbeg + (it + 1) * 16);
-            // all operands of the stage into registers first, then the MFMAs
-            // back to back (no branches between them)
+        // one stage for the blocks [JLO, JHI): all operands into registers
+        // first, then the MFMAs back to back (no branches between them)
+        auto body = [&](auto lo_c, auto hi_c) {
+            constexpr int JLO = decltype(lo_c)::value < T ? decltype(lo_c)::value : T;
+            constexpr int JHI = decltype(hi_c)::value < T ? decltype(hi_c)::value : T;
+            if constexpr (JHI > JLO) {
+                double av[4], bv[4][T];
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) {
+                    const int k = ks * 4 + lk;
+                    av[ks] = As[k][16 * w + lr];
+#pragma unroll
+                    for (int j = JLO; j < JHI; ++j) bv[ks][j] = Bs[k][16 * j + lr];
+                }
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+                    for (int j = JLO; j < JHI; ++j)
+                        acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], bv[ks][j], acc[j], 0, 0, 0);
+            }
+        };
+        auto body_any = [&](int lo, int hi) {
             double av[4], bv[4][T];
 #pragma unroll
             for (int ks = 0; ks < 4; ++ks) {
@@ -445,7 +517,40 @@ __global__ __launch_bounds__(64 * T) void gemm_strip_kernel(
             for (int ks = 0; ks < 4; ++ks)
 #pragma unroll
                 for (int j = 0; j < T; ++j)
-                    acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], bv[ks][j], acc[j], 0, 0, 0);
+                    if (j >= lo && j < hi)
+                        acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], bv[ks][j], acc[j], 0, 0, 0);
+        };
+        for (int it = 0; it < nk; ++it) {
+            const int k0 = kbeg + it * 16;
+            if (it + 1 < nk) load(k0 + 16);
+            int jlo = 0;
+            if (KMODE == 2 && k0 >= n0) jlo = min(T, (k0 - n0) / 16);
+            if (jlo >= jhi) {
+                // nothing to do for this wave in this stage
+            } else if (jhi == T) {
+                switch (jlo) {
+                    case 0: body(std::integral_constant<int, 0>{}, std::integral_constant<int, T>{}); break;
+                    case 1: body(std::integral_constant<int, 1>{}, std::integral_constant<int, T>{}); break;
+                    case 2: body(std::integral_constant<int, 2>{}, std::integral_constant<int, T>{}); break;
+                    case 3: body(std::integral_constant<int, 3>{}, std::integral_constant<int, T>{}); break;
+                    case 4: body(std::integral_constant<int, 4>{}, std::integral_constant<int, T>{}); break;
+                    case 5: body(std::integral_constant<int, 5>{}, std::integral_constant<int, T>{}); break;
+                    case 6: body(std::integral_constant<int, 6>{}, std::integral_constant<int, T>{}); break;
+                    default: body(std::integral_constant<int, 7>{}, std::integral_constant<int, T>{}); break;
+                }
+            } else if (jlo == 0) {
+                switch (jhi) {
+                    case 1: body(std::integral_constant<int, 0>{}, std::integral_constant<int, 1>{}); break;
+                    case 2: body(std::integral_constant<int, 0>{}, std::integral_constant<int, 2>{}); break;
+                    case 3: body(std::integral_constant<int, 0>{}, std::integral_constant<int, 3>{}); break;
+                    case 4: body(std::integral_constant<int, 0>{}, std::integral_constant<int, 4>{}); break;
+                    case 5: body(std::integral_constant<int, 0>{}, std::integral_constant<int, 5>{}); break;
+                    case 6: body(std::integral_constant<int, 0>{}, std::integral_constant<int, 6>{}); break;
+                    default: body(std::integral_constant<int, 0>{}, std::integral_constant<int, 7>{}); break;
+                }
+            } else {
+                body_any(jlo, jhi);
+            }
             __syncthreads();
             if (it + 1 < nk) {
                 store();
@@ -456,7 +561,7 @@ __global__ __launch_bounds__(64 * T) void gemm_strip_kernel(
     const int lq = lane >> 4;
 #pragma unroll
     for (int j = 0; j < T; ++j) {
-        if (j > jmax) continue;
+        if (j >= jhi) continue;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int row = m0 + 16 * w + 4 * r + lq;

@@ -49,6 +49,7 @@ struct elmddm_plan {
     elmddm_problem p{};
     int B = 1;    // problem instances per solve (same geometry)
     int gram_code = -2;   // kernel for the Gram products (see gram_product)
+    float tune_ms[2][9] = {};   // last autotune: Gram / triangular-solve time per candidate
     int trsm_code = -2;   // kernel for the triangular-solve products
     bool env_fused = true;
     int mode = ELMDDM_MODE_FP64;
@@ -1012,7 +1013,8 @@ elmddm_status elmddm_autotune(elmddm_plan* P, void* stream, int32_t* choice)
         return ms;
     };
     float best_g = 1e30f, best_t = 1e30f;
-    for (int code : codes) {
+    for (int ci = 0; ci < 9; ++ci) {
+        const int code = codes[ci];
         const float tg = time_it([&] {
             gram_product(st, code, n, P->gram_rows, P->X0, ldx, P->sX, P->G, ldg, P->sG, N);
         });
@@ -1027,6 +1029,8 @@ elmddm_status elmddm_autotune(elmddm_plan* P, void* stream, int32_t* choice)
             best_t = tt;
             P->trsm_code = code;
         }
+        P->tune_ms[0][ci] = 0.5f * tg;
+        P->tune_ms[1][ci] = 0.5f * tt;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1087,6 +1091,18 @@ elmddm_status elmddm_stage_times(elmddm_plan* P, double* ms, int32_t* solves)
     P->harvest();
     for (int i = 0; i < ELMDDM_NUM_STAGES; ++i) ms[i] = P->stage_ms[i];
     if (solves) *solves = P->timed_solves;
+    return ELMDDM_OK;
+}
+
+elmddm_status elmddm_autotune_times(const elmddm_plan* P, int32_t* codes, double* gram_ms, double* trsm_ms)
+{
+    if (!P || !codes || !gram_ms || !trsm_ms) return fail(ELMDDM_INVALID_ARG, "NULL argument");
+    const int cs[] = {-1, -2, -3, -4, 4, 5, 6, 7, 8};
+    for (int i = 0; i < 9; ++i) {
+        codes[i] = cs[i];
+        gram_ms[i] = P->tune_ms[0][i];
+        trsm_ms[i] = P->tune_ms[1][i];
+    }
     return ELMDDM_OK;
 }
 
