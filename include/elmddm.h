@@ -130,6 +130,10 @@ elmddm_status elmddm_plan_create(const elmddm_problem* problem, elmddm_plan** pl
 elmddm_status elmddm_plan_create_batch(const elmddm_problem* problem, int32_t batch,
                                        elmddm_plan** plan);
 
+/* Sizes (including device_bytes) that elmddm_plan_create_batch would give,
+ * computed on the host without allocating anything. */
+elmddm_status elmddm_plan_query(const elmddm_problem* problem, int32_t batch, elmddm_sizes* sizes);
+
 /* Release the plan and its device memory.  NULL is accepted. */
 elmddm_status elmddm_plan_destroy(elmddm_plan* plan);
 
@@ -332,6 +336,39 @@ elmddm_status elmddm_mlp_train(elmddm_mlp* mlp, int32_t nsamples, const float* X
 /* Prediction in float64: out [batch][out_dim] = scale * y. */
 elmddm_status elmddm_mlp_predict(elmddm_mlp* mlp, int32_t batch, const float* x, double scale, double* out,
                                  void* stream);
+
+/* ------------------------------------------------------------------------
+ * Ragged batches in one graph launch.  Problems of different shapes (grid,
+ * neurons, points, operator) go to different plans (each a batch of
+ * same-shape instances); elmddm_graph_capture records the solves
+ * elmddm_solve(plans[i], args[i]) for i = 0..nsolves-1, in this order, into
+ * one HIP graph.  A plan may appear several times (e.g. one chunk of its
+ * shape after another): its solves run one after the other and reuse its
+ * workspace.  elmddm_graph_launch replays every solve with one graph launch
+ * on the caller's stream; the input and output buffers named in args must
+ * stay valid for as long as the graph is launched.  Capture enqueues nothing
+ * (it records on a private stream) and needs stage timing off on every plan.
+ * After a launch each plan's workspace holds the factors of its last solve in
+ * the graph.  elmddm_graph_info synchronises the launch stream and reports
+ * solve i as elmddm_solve_info would.
+ * ------------------------------------------------------------------------ */
+typedef struct elmddm_solve_args {
+    const double* W;
+    const double* b;
+    const double* f;
+    const double* g;
+    const double* coef;
+    double* u_gamma;
+    double* c;
+} elmddm_solve_args;
+
+typedef struct elmddm_graph elmddm_graph;
+
+elmddm_status elmddm_graph_capture(elmddm_plan* const* plans, const elmddm_solve_args* args, int32_t nsolves,
+                                   elmddm_graph** graph);
+elmddm_status elmddm_graph_launch(elmddm_graph* graph, void* stream);
+elmddm_status elmddm_graph_info(elmddm_graph* graph, int32_t solve, elmddm_info* info);
+elmddm_status elmddm_graph_destroy(elmddm_graph* graph);
 
 const char* elmddm_status_string(elmddm_status status);
 const char* elmddm_last_error(void);

@@ -40,6 +40,8 @@ EXPORTED = [
     "elmddm_mlp_create", "elmddm_mlp_destroy", "elmddm_mlp_num_params", "elmddm_mlp_set_params",
     "elmddm_mlp_get_params", "elmddm_mlp_forward", "elmddm_mlp_loss_grad", "elmddm_mlp_adam_step",
     "elmddm_mlp_train", "elmddm_mlp_predict",
+    "elmddm_plan_query", "elmddm_graph_capture", "elmddm_graph_launch", "elmddm_graph_info",
+    "elmddm_graph_destroy",
     "elmddm_status_string", "elmddm_last_error",
 ]
 
@@ -65,6 +67,11 @@ class Sizes(ctypes.Structure):
 class Info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("bad_subdomain", ctypes.c_int32),
                 ("bad_pass", ctypes.c_int32), ("bad_instance", ctypes.c_int32)]
+
+
+class SolveArgs(ctypes.Structure):
+    _fields_ = [("W", ctypes.c_void_p), ("b", ctypes.c_void_p), ("f", ctypes.c_void_p), ("g", ctypes.c_void_p),
+                ("coef", ctypes.c_void_p), ("u_gamma", ctypes.c_void_p), ("c", ctypes.c_void_p)]
 
 
 class ElmddmError(RuntimeError):
@@ -107,6 +114,11 @@ def lib():
                                           ctypes.POINTER(ctypes.c_double), vp]
         L.elmddm_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]
         L.elmddm_pass_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]
+        L.elmddm_plan_query.argtypes = [ctypes.POINTER(Problem), i32, ctypes.POINTER(Sizes)]
+        L.elmddm_graph_capture.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(SolveArgs), i32, ctypes.POINTER(vp)]
+        L.elmddm_graph_launch.argtypes = [vp, vp]
+        L.elmddm_graph_info.argtypes = [vp, i32, ctypes.POINTER(Info)]
+        L.elmddm_graph_destroy.argtypes = [vp]
         f32 = ctypes.c_float
         L.elmddm_mlp_create.argtypes = [i32, i32, i32, i32, ctypes.POINTER(vp)]
         L.elmddm_mlp_destroy.argtypes = [vp]
@@ -329,3 +341,52 @@ class MLP:
         import torch
         _check(lib().elmddm_mlp_predict(self._h, batch, _ptr_t(x, torch.float32), scale,
                                         _ptr_t(out, torch.float64), _stream()))
+
+
+def plan_query(problem: Problem, batch: int = 1) -> Sizes:
+    """Sizes of a plan (device bytes included) without allocating it."""
+    s = Sizes()
+    _check(lib().elmddm_plan_query(ctypes.byref(problem), batch, ctypes.byref(s)))
+    return s
+
+
+class Graph:
+    """Solves of several plans captured into one HIP graph (one launch)."""
+
+    def __init__(self, solves):
+        """solves: list of (Plan, dict(W=, b=, f=, g=, coef=, u_gamma=, c=)) with device tensors
+        (g, coef may be None).  The tensors are kept alive with the graph."""
+        n = len(solves)
+        plans = (ctypes.c_void_p * n)(*[p._h.value for p, _ in solves])
+        args = (SolveArgs * n)()
+        self._keep = []
+        for i, (_, a) in enumerate(solves):
+            ptrs = {}
+            for k in ("W", "b", "f", "g", "coef", "u_gamma", "c"):
+                t = a.get(k)
+                ptrs[k] = _ptr(t).value if t is not None else None
+                self._keep.append(t)
+            args[i] = SolveArgs(**ptrs)
+        self._plans = [p for p, _ in solves]
+        self._h = ctypes.c_void_p()
+        _check(lib().elmddm_graph_capture(plans, args, n, ctypes.byref(self._h)))
+        self.n = n
+
+    def launch(self):
+        _check(lib().elmddm_graph_launch(self._h, _stream()))
+
+    def info(self, i) -> Info:
+        inf = Info()
+        _check(lib().elmddm_graph_info(self._h, i, ctypes.byref(inf)))
+        return inf
+
+    def close(self):
+        if self._h:
+            lib().elmddm_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

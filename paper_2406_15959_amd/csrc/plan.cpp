@@ -105,11 +105,17 @@ struct elmddm_plan {
     double pass_ms[9] = {};   // per CholeskyQR pass: Gram, Cholesky + inverses, triangular solve
     int timed_solves = 0;
 
+    bool dry = false;   // size query only: count bytes, allocate nothing
+
     template <class T>
     elmddm_status dalloc(T** ptr, size_t count)
     {
         *ptr = nullptr;
         if (count == 0) count = 1;
+        if (dry) {
+            bytes += count * sizeof(T);
+            return ELMDDM_OK;
+        }
         void* q = nullptr;
         if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) {
             (void)hipGetLastError();
@@ -125,7 +131,7 @@ struct elmddm_plan {
     elmddm_status upload(T** ptr, const std::vector<T>& v)
     {
         elmddm_status st = dalloc(ptr, v.size());
-        if (st != ELMDDM_OK) return st;
+        if (st != ELMDDM_OK || dry) return st;
         if (!v.empty() && hipMemcpy(*ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
             return fail(ELMDDM_HIP_ERROR, "hipMemcpy failed during plan creation");
         return ELMDDM_OK;
@@ -528,6 +534,7 @@ elmddm_status build(elmddm_plan* P)
     TRY(P->dalloc(&P->bs1, NT * n));
     TRY(P->dalloc(&P->bs2, NT * n));
     TRY(P->dalloc(&P->d_info, 1));
+    if (P->dry) return ELMDDM_OK;
     // The strictly upper parts of the inverse factors are never written by the
     // solve and must read as zero.
     for (int i = 0; i < 3; ++i)
@@ -608,6 +615,26 @@ elmddm_status elmddm_plan_create_batch(const elmddm_problem* problem, int32_t ba
     }
     *plan = P;
     return ELMDDM_OK;
+}
+
+elmddm_status elmddm_plan_query(const elmddm_problem* problem, int32_t batch, elmddm_sizes* sizes)
+{
+    if (!sizes) return fail(ELMDDM_INVALID_ARG, "sizes is NULL");
+    elmddm_status st = validate(problem);
+    if (st != ELMDDM_OK) return st;
+    if (batch < 1 || (int64_t)batch * problem->nsub_x * problem->nsub_y > (1 << 20))
+        return fail(ELMDDM_INVALID_ARG, "batch must be >= 1 and batch * nsub <= 2^20");
+    elmddm_plan Q;
+    Q.p = *problem;
+    Q.B = batch;
+    Q.dry = true;
+    try {
+        st = build(&Q);
+    } catch (const std::bad_alloc&) {
+        st = fail(ELMDDM_OOM, "host allocation failed while building the layout");
+    }
+    if (st != ELMDDM_OK) return st;
+    return elmddm_plan_sizes(&Q, sizes);
 }
 
 elmddm_status elmddm_plan_destroy(elmddm_plan* plan)
@@ -1134,3 +1161,119 @@ const char* elmddm_status_string(elmddm_status s)
 const char* elmddm_last_error(void) { return g_last_error.c_str(); }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Whole solves captured into one HIP graph.
+// ---------------------------------------------------------------------------
+struct elmddm_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<elmddm_plan*> plans;     // per captured solve
+    DevInfo* d_infos = nullptr;          // per captured solve: copy of its status word
+    hipStream_t last = nullptr;
+    bool launched = false;
+    ~elmddm_graph()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (d_infos) (void)hipFree(d_infos);
+    }
+};
+
+elmddm_status elmddm_graph_capture(elmddm_plan* const* plans, const elmddm_solve_args* args, int32_t nsolves,
+                                   elmddm_graph** out)
+{
+    if (!out) return fail(ELMDDM_INVALID_ARG, "graph output pointer is NULL");
+    *out = nullptr;
+    if (!plans || !args || nsolves < 1) return fail(ELMDDM_INVALID_ARG, "no solves to capture");
+    for (int i = 0; i < nsolves; ++i) {
+        if (!plans[i]) return fail(ELMDDM_INVALID_ARG, "NULL plan");
+        if (plans[i]->timing) return fail(ELMDDM_INVALID_ARG, "stage timing must be off while capturing");
+    }
+    elmddm_graph* G = new (std::nothrow) elmddm_graph();
+    if (!G) return fail(ELMDDM_OOM, "host allocation failed");
+    if (hipMalloc((void**)&G->d_infos, nsolves * sizeof(DevInfo)) != hipSuccess) {
+        (void)hipGetLastError();
+        delete G;
+        return fail(ELMDDM_OOM, "hipMalloc of the graph status words failed");
+    }
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+        delete G;
+        return check_launch("graph capture stream");
+    }
+    elmddm_status est = ELMDDM_OK;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        est = check_launch("hipStreamBeginCapture");
+    } else {
+        for (int i = 0; i < nsolves && est == ELMDDM_OK; ++i) {
+            const elmddm_solve_args& a = args[i];
+            est = elmddm_solve(plans[i], a.W, a.b, a.f, a.g, a.coef, a.u_gamma, a.c, cs);
+            if (est == ELMDDM_OK &&
+                hipMemcpyAsync(G->d_infos + i, plans[i]->d_info, sizeof(DevInfo), hipMemcpyDeviceToDevice, cs) !=
+                    hipSuccess)
+                est = check_launch("graph status copy");
+            G->plans.push_back(plans[i]);
+        }
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(cs, &g);
+        if (est == ELMDDM_OK && e != hipSuccess) est = check_launch("hipStreamEndCapture");
+        G->graph = g;
+        if (est == ELMDDM_OK && hipGraphInstantiate(&G->exec, g, nullptr, nullptr, 0) != hipSuccess)
+            est = check_launch("hipGraphInstantiate");
+    }
+    (void)hipStreamDestroy(cs);
+    // the workspaces hold nothing until the graph runs
+    for (int i = 0; i < nsolves; ++i) {
+        plans[i]->factors_valid = false;
+        plans[i]->schur_valid = false;
+        plans[i]->last_stream = nullptr;
+        plans[i]->solved = false;
+    }
+    if (est != ELMDDM_OK) {
+        delete G;
+        return est;
+    }
+    *out = G;
+    return ELMDDM_OK;
+}
+
+elmddm_status elmddm_graph_launch(elmddm_graph* G, void* stream)
+{
+    if (!G || !G->exec) return fail(ELMDDM_INVALID_ARG, "NULL graph");
+    hipStream_t st = (hipStream_t)stream;
+    if (hipGraphLaunch(G->exec, st) != hipSuccess) return check_launch("hipGraphLaunch");
+    G->last = st;
+    G->launched = true;
+    // every plan's workspace now holds the factors of its last solve in the graph
+    for (elmddm_plan* P : G->plans) {
+        P->factors_valid = true;
+        P->schur_valid = P->keep_schur && P->Skeep;
+        P->last_stream = st;
+        P->solved = true;
+    }
+    return ELMDDM_OK;
+}
+
+elmddm_status elmddm_graph_info(elmddm_graph* G, int32_t i, elmddm_info* info)
+{
+    if (!G || !info) return fail(ELMDDM_INVALID_ARG, "NULL argument");
+    if (i < 0 || i >= (int)G->plans.size()) return fail(ELMDDM_INVALID_ARG, "solve index out of range");
+    if (!G->launched) return fail(ELMDDM_INVALID_ARG, "the graph has not been launched");
+    if (hipStreamSynchronize(G->last) != hipSuccess) return check_launch("graph_info sync");
+    DevInfo h{};
+    if (hipMemcpy(&h, G->d_infos + i, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess)
+        return check_launch("graph_info copy");
+    const elmddm_plan* P = G->plans[i];
+    info->status = h.status;
+    info->bad_subdomain = h.bad_subdomain == INT_MAX ? -1 : h.bad_subdomain % P->N;
+    info->bad_pass = h.bad_pass;
+    info->bad_instance = h.bad_subdomain == INT_MAX ? -1 : h.bad_subdomain / P->N;
+    return ELMDDM_OK;
+}
+
+elmddm_status elmddm_graph_destroy(elmddm_graph* G)
+{
+    delete G;
+    return ELMDDM_OK;
+}

@@ -66,3 +66,27 @@ def test_plan_create_rejects_too_few_interior_points():
         B.Plan(p)
     assert e.value.status == B.INVALID_ARG
     assert b"neurons" in B.lib().elmddm_last_error()
+
+
+def test_plan_query_sizes_without_a_gpu():
+    """The size query builds the layout on the host only."""
+    _lib_path()
+    from paper_2406_15959_amd import binding as B
+    p = B.make_problem(nsub_x=3, nsub_y=2, neurons=30, q_x=8, q_y=8, m_bdry_edge=6, m_ifc_edge=5)
+    s1 = B.plan_query(p, 1)
+    s3 = B.plan_query(p, 3)
+    assert s1.nsub == 6 and s1.neurons == 30 and s1.batch == 1 and s3.batch == 3
+    assert s1.n_interface == ((3 - 1) * 2 + 3 * (2 - 1)) * 5
+    assert s1.device_bytes > 0 and s3.device_bytes > 2 * s1.device_bytes
+    with pytest.raises(B.ElmddmError):
+        B.plan_query(p, 0)
+
+
+def test_ragged_problem_draws_are_reproducible_and_cover_the_shapes():
+    import workload as wl
+    a = wl.ragged_problems(64)
+    b = wl.ragged_problems(64)
+    assert a == b
+    assert {P.nsub_x for P in a} == {4, 8, 16} and {P.neurons for P in a} == {100, 200, 400, 800}
+    for P in a:
+        assert P.q_x ** 2 >= P.neurons and P.op == wl.OP_VARCOEF and 1 <= P.k1 <= 3

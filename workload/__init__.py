@@ -269,3 +269,25 @@ def mlp_init(dims, seed: int):
         parts.append(rng.uniform(-lim, lim, fo * fi))
         parts.append(rng.uniform(-lim, lim, fo))
     return np.concatenate(parts).astype(np.float32)
+
+
+# ---------------------------------------------------------------------------
+# Ragged batch of independent variable-coefficient problems: subdomain grid
+# from {4x4, 8x8, 16x16}, neurons per subdomain from {100, 200, 400, 800},
+# k1, k2 from {1, 2, 3}; q = round(2 sqrt(n)) interior points per direction
+# (q^2 ~ 4n), q points per edge, weights and biases U[-sqrt(n)/5, sqrt(n)/5].
+# ---------------------------------------------------------------------------
+
+def ragged_problems(count: int = 256, seed: int = 3000, grids=(4, 8, 16), neurons=(100, 200, 400, 800)):
+    """Problem p is drawn from numpy.random.default_rng([seed, p]); its hidden
+    layer seed is seed + p."""
+    out = []
+    for p in range(count):
+        rng = np.random.default_rng([seed, p])
+        g = int(grids[rng.integers(len(grids))])
+        n = int(neurons[rng.integers(len(neurons))])
+        k1, k2 = (int(v) for v in rng.integers(1, 4, size=2))
+        q = int(round(2.0 * math.sqrt(n)))
+        out.append(Problem(nsub_x=g, nsub_y=g, neurons=n, q_x=q, q_y=q, m_bdry_edge=q, m_ifc_edge=q,
+                           op=OP_VARCOEF, R=math.sqrt(n) / 5.0, k1=k1, k2=k2))
+    return out
