@@ -149,9 +149,25 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(
     const unsigned total = gx * gy * gridDim.z;
     const unsigned p = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
     const unsigned q = (!XCD || (total & 7u)) ? p : (p & 7u) * (total >> 3) + (p >> 3);
-    const int tm = q % gx, tn = (q / gx) % gy;
-    const long long z = q / (gx * gy);
-    if (LOWER && tm < tn) return;
+    int tm, tn;
+    long long z;
+    if (LOWER && M == N) {
+        // triangular launch: gx = g (g + 1) / 2 lower tiles per matrix, column by column
+        z = q / gx;
+        int t = q % gx;
+        const int g = (GB_M + M - 1) / GB_M;
+        tn = 0;
+        while (t >= g - tn) {
+            t -= g - tn;
+            ++tn;
+        }
+        tm = tn + t;
+    } else {
+        tm = q % gx;
+        tn = (q / gx) % gy;
+        z = q / (gx * gy);
+        if (LOWER && tm < tn) return;
+    }
     A += z * sA;
     B += z * sB;
     C += z * sC;
@@ -160,8 +176,17 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(
     if (KMODE == 1) kbeg = n0 < K ? n0 : K;
     if (KMODE == 2) kend = (n0 + GB_N) < K ? (n0 + GB_N) : K;
 
-    __shared__ CT As[GB_K][GB_M + PAD];
-    __shared__ CT Bs[GB_K][GB_N + PAD];
+    // An operand that is loaded along k (A with TA, B without TB) is staged
+    // k-contiguous per row: stores are contiguous and the MFMA reads of the 16
+    // rows x 2 k of a half-wave fall in distinct banks (row stride GB_K + 2
+    // doubles or GB_K + 4 floats); the other layout is k-major with padded rows.
+    constexpr bool AK = TA, BK = !TB;
+    constexpr int SK = GB_K + (F64 ? 2 : 4);
+    constexpr int SM = GB_M + PAD;
+    __shared__ __attribute__((aligned(16))) CT As_[AK ? GB_M * SK : GB_K * SM];
+    __shared__ __attribute__((aligned(16))) CT Bs_[BK ? GB_N * SK : GB_K * SM];
+    auto As = [&](int k, int m) -> CT& { return AK ? As_[m * SK + k] : As_[k * SM + m]; };
+    auto Bs = [&](int k, int nn) -> CT& { return BK ? Bs_[nn * SK + k] : Bs_[k * SM + nn]; };
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -215,20 +240,20 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(
         if (!TA) {
             const int k = tid / RS, m = (tid % RS) * V;
 #pragma unroll
-            for (int e = 0; e < V; ++e) As[k][m + e] = (CT)ra[e];
+            for (int e = 0; e < V; ++e) As(k, m + e) = (CT)ra[e];
         } else {
             const int m = tid >> 2, k = (tid & 3) * V;
 #pragma unroll
-            for (int e = 0; e < V; ++e) As[k + e][m] = (CT)ra[e];
+            for (int e = 0; e < V; ++e) As(k + e, m) = (CT)ra[e];
         }
         if (!TB) {
             const int nn = tid >> 2, k = (tid & 3) * V;
 #pragma unroll
-            for (int e = 0; e < V; ++e) Bs[k + e][nn] = (CT)rb[e];
+            for (int e = 0; e < V; ++e) Bs(k + e, nn) = (CT)rb[e];
         } else {
             const int k = tid / RS, nn = (tid % RS) * V;
 #pragma unroll
-            for (int e = 0; e < V; ++e) Bs[k][nn + e] = (CT)rb[e];
+            for (int e = 0; e < V; ++e) Bs(k, nn + e) = (CT)rb[e];
         }
     };
 
@@ -256,10 +281,10 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(
 #pragma unroll
         for (int ks = 0; ks < GB_K / 4; ++ks) {
             const int k = ks * 4 + lk;
-            if constexpr ((MK & 3) != 0) av[ks][0] = As[k][wm * 32 + lr];
-            if constexpr ((MK & 12) != 0) av[ks][1] = As[k][wm * 32 + 16 + lr];
-            if constexpr ((MK & 5) != 0) bv[ks][0] = Bs[k][wn * 32 + lr];
-            if constexpr ((MK & 10) != 0) bv[ks][1] = Bs[k][wn * 32 + 16 + lr];
+            if constexpr ((MK & 3) != 0) av[ks][0] = As(k, wm * 32 + lr);
+            if constexpr ((MK & 12) != 0) av[ks][1] = As(k, wm * 32 + 16 + lr);
+            if constexpr ((MK & 5) != 0) bv[ks][0] = Bs(k, wn * 32 + lr);
+            if constexpr ((MK & 10) != 0) bv[ks][1] = Bs(k, wn * 32 + 16 + lr);
         }
 #pragma unroll
         for (int ks = 0; ks < GB_K / 4; ++ks) {
@@ -343,6 +368,7 @@ static void gemm_launch(hipStream_t st, int M, int N, int K, double alpha, const
                         double* C, int ldc, long long sC, int batch)
 {
     dim3 grid((M + GB_M - 1) / GB_M, (N + GB_N - 1) / GB_N, batch);
+    if (LOWER && M == N) grid = dim3(grid.x * (grid.x + 1) / 2, 1, batch);   // lower tiles only
     hipLaunchKernelGGL((gemm_mfma_kernel<CT, TA, TB, KMODE, LOWER, BK, XCD>), grid, dim3(256), 0, st, M,
                        N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
 }
