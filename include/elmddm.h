@@ -106,7 +106,7 @@ typedef struct elmddm_sizes {
 typedef struct elmddm_info {
     int32_t status;          /* elmddm_status of the last solve                 */
     int32_t bad_subdomain;   /* first subdomain whose local factorisation failed, else -1 */
-    int32_t bad_pass;        /* CholeskyQR pass (1..3) of that failure, else 0  */
+    int32_t bad_pass;        /* CholeskyQR pass (1..4) of that failure, else 0  */
     int32_t bad_instance;    /* problem instance of that failure, else -1       */
 } elmddm_info;
 
@@ -153,7 +153,8 @@ elmddm_status elmddm_points(const elmddm_plan* plan, int32_t kind, double* xy, i
  *   coef  [3][nsub][q_x*q_y]  a, da/dx, da/dy at the interior points (VARCOEF only; else NULL)
  *   u_gamma [n_interface]     output: interface variable
  *   c     [nsub][neurons]     output: output-layer coefficients of every local network
- * Local least squares: three-pass shifted CholeskyQR in float64 (Gram by
+ * Local least squares: shifted CholeskyQR (3 or 4 passes, see
+ * elmddm_plan_set_passes) in float64 (Gram by
  * MFMA, Cholesky, triangular solves); interface system: dense float64
  * Cholesky.  Enqueued on stream; check elmddm_solve_info afterwards. */
 elmddm_status elmddm_solve(elmddm_plan* plan, const double* W, const double* b, const double* f,
@@ -227,6 +228,14 @@ elmddm_status elmddm_schur_rhs(elmddm_plan* plan, int32_t nrhs, const double* f,
 elmddm_status elmddm_interface_cg(elmddm_plan* plan, int32_t nrhs, const double* rhs, double* u, double tol,
                                   int32_t maxit, int32_t* iters, double* relres, void* stream);
 
+/* Number of CholeskyQR passes of the local least squares (3 or 4; passes
+ * 1 .. npass - 2 carry the diagonal shift, the last one also yields h).  One
+ * shifted pass handles column-scaled condition numbers of K^s up to about
+ * 1e12, two up to about 1e15.  Default: 4 for neurons >= 600, else 3 (the
+ * tanh feature blocks of the configured scales reach 1e12..1e13 at 800
+ * neurons).  Allocates a fourth inverse factor on first use. */
+elmddm_status elmddm_plan_set_passes(elmddm_plan* plan, int32_t npass);
+
 /* Precision mode of later solves on this plan.
  *  ELMDDM_MODE_FP64 (default): every product in float64.
  *  ELMDDM_MODE_MIXED: the Gram matrices of the first CholeskyQR pass are
@@ -277,7 +286,8 @@ elmddm_status elmddm_stage_times(elmddm_plan* plan, double* ms, int32_t* solves)
 /* The local-factorisation stages split by CholeskyQR pass (same timing
  * switch and totals as elmddm_stage_times): ms[3 p + 0] Gram product,
  * ms[3 p + 1] Cholesky + inverses, ms[3 p + 2] triangular solve of pass
- * p + 1 (p = 0, 1, 2), in milliseconds summed over the timed solves. */
+ * p + 1 (p = 0 .. 3; zeros beyond the plan's pass count), in milliseconds
+ * summed over the timed solves.  ms holds 12 doubles. */
 elmddm_status elmddm_pass_times(elmddm_plan* plan, double* ms, int32_t* solves);
 
 /* ------------------------------------------------------------------------

@@ -35,7 +35,7 @@ EXPORTED = [
     "elmddm_plan_create", "elmddm_plan_create_batch", "elmddm_plan_destroy", "elmddm_plan_sizes", "elmddm_points",
     "elmddm_solve", "elmddm_solve_info", "elmddm_eval", "elmddm_assemble",
     "elmddm_plan_keep_schur", "elmddm_get_schur", "elmddm_set_timing", "elmddm_stage_times", "elmddm_pass_times",
-    "elmddm_autotune", "elmddm_autotune_times", "elmddm_plan_set_mode", "elmddm_plan_reserve_rhs", "elmddm_solve_rhs",
+    "elmddm_autotune", "elmddm_autotune_times", "elmddm_plan_set_mode", "elmddm_plan_set_passes", "elmddm_plan_reserve_rhs", "elmddm_solve_rhs",
     "elmddm_schur_rhs", "elmddm_interface_cg",
     "elmddm_mlp_create", "elmddm_mlp_destroy", "elmddm_mlp_num_params", "elmddm_mlp_set_params",
     "elmddm_mlp_get_params", "elmddm_mlp_forward", "elmddm_mlp_loss_grad", "elmddm_mlp_adam_step",
@@ -105,6 +105,7 @@ def lib():
         L.elmddm_set_timing.argtypes = [vp, i32]
         L.elmddm_autotune.argtypes = [vp, vp, ctypes.POINTER(i32)]
         L.elmddm_plan_set_mode.argtypes = [vp, i32]
+        L.elmddm_plan_set_passes.argtypes = [vp, i32]
         L.elmddm_autotune_times.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double),
                                             ctypes.POINTER(ctypes.c_double)]
         L.elmddm_plan_reserve_rhs.argtypes = [vp, i32]
@@ -275,11 +276,14 @@ class Plan:
         return list(ms), n.value
 
     def pass_times(self):
-        """([[gram, cholesky, trsm] ms for passes 1..3] summed over timed solves, number of solves)."""
-        ms = (ctypes.c_double * 9)()
+        """([[gram, cholesky, trsm] ms for passes 1..4] summed over timed solves, number of solves)."""
+        ms = (ctypes.c_double * 12)()
         n = ctypes.c_int32()
         _check(lib().elmddm_pass_times(self._h, ms, ctypes.byref(n)))
-        return [list(ms[3 * p:3 * p + 3]) for p in range(3)], n.value
+        return [list(ms[3 * p:3 * p + 3]) for p in range(4)], n.value
+
+    def set_passes(self, npass):
+        _check(lib().elmddm_plan_set_passes(self._h, npass))
 
     def get_schur(self, S, rhs):
         _check(lib().elmddm_get_schur(self._h, _ptr(S), _ptr(rhs), _stream()))

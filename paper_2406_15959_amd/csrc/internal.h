@@ -140,8 +140,8 @@ void unpermute_matrix(hipStream_t st, int nE, int mg, const int32_t* perm, const
 
 void local_backsolve(hipStream_t st, int N, int ngeo, long long nG, int n, int kpad, const double* X,
                      int ldx, long long sX, int mI, int hrow, const int32_t* gidx, const double* u,
-                     const double* Linv1, const double* Linv2, const double* Linv3, int ldg,
-                     long long sG, double* c, double* tmp1, double* tmp2);
+                     double* const* Linv, int npass, int ldg, long long sG, double* c, double* tmp1,
+                     double* tmp2);
 
 void eval_points(hipStream_t st, int npts, const double* xy, int nx, int ny, double x0, double x1,
                  double y0, double y1, int n, const double* W, const double* b, const double* c,

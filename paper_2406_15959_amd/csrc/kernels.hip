@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <type_traits>
+#include <utility>
 
 #include "internal.h"
 
@@ -1495,15 +1496,19 @@ __global__ __launch_bounds__(256) void trmv_t_kernel(int n, const double* Li, in
 
 void local_backsolve(hipStream_t st, int N, int ngeo, long long nG, int n, int kpad, const double* X,
                      int ldx, long long sX, int mI, int hrow, const int32_t* gidx, const double* u,
-                     const double* Linv1, const double* Linv2, const double* Linv3, int ldg,
-                     long long sG, double* c, double* tmp1, double* tmp2)
+                     double* const* Linv, int npass, int ldg, long long sG, double* c, double* tmp1,
+                     double* tmp2)
 {
     dim3 grid((n + 3) / 4, N);
     hipLaunchKernelGGL(bs_rhs_kernel, grid, dim3(256), 0, st, n, kpad, X, ldx, sX, mI, hrow, gidx, u,
                        tmp1, ngeo, nG);
-    hipLaunchKernelGGL(trmv_t_kernel, grid, dim3(256), 0, st, n, Linv3, ldg, sG, tmp1, tmp2);
-    hipLaunchKernelGGL(trmv_t_kernel, grid, dim3(256), 0, st, n, Linv2, ldg, sG, tmp2, tmp1);
-    hipLaunchKernelGGL(trmv_t_kernel, grid, dim3(256), 0, st, n, Linv1, ldg, sG, tmp1, c);
+    double* cur = tmp1;
+    double* nxt = tmp2;
+    for (int q = npass - 1; q >= 0; --q) {
+        double* out = q == 0 ? c : nxt;
+        hipLaunchKernelGGL(trmv_t_kernel, grid, dim3(256), 0, st, n, Linv[q], ldg, sG, cur, out);
+        std::swap(cur, nxt);
+    }
 }
 
 // u[E*mg + r] = up[perm[E]*mg + r]

@@ -69,7 +69,13 @@ struct elmddm_plan {
     // device memory
     std::vector<void*> allocs;
     uint64_t bytes = 0;
-    double *X0 = nullptr, *X1 = nullptr, *G = nullptr, *Linv[3] = {nullptr, nullptr, nullptr};
+    double *X0 = nullptr, *X1 = nullptr, *G = nullptr, *Linv[4] = {nullptr, nullptr, nullptr, nullptr};
+    // CholeskyQR passes (3 or 4): passes 1 .. npass - 2 are shifted, the last
+    // one also factors the rhs row.  After a solve, Qprev holds Q of pass
+    // npass - 1 (all rows) and Xfin the last pass's interface rows, h row and
+    // flux rows.
+    int npass = 3;
+    double *Qprev = nullptr, *Xfin = nullptr;
     double *Dinv = nullptr, *Tbuf = nullptr, *P = nullptr, *Mbuf = nullptr, *abuf = nullptr;
     double *Sx = nullptr, *Skeep = nullptr, *DinvS = nullptr, *yvec = nullptr, *dsave = nullptr;
     double *uperm = nullptr, *bs1 = nullptr, *bs2 = nullptr, *SL = nullptr;
@@ -98,11 +104,11 @@ struct elmddm_plan {
     // stage timing
     bool timing = false;
     hipEvent_t ev[ELMDDM_NUM_STAGES + 1] = {};
-    hipEvent_t pev[10] = {};  // per-pass Gram / Cholesky / triangular-solve boundaries
+    hipEvent_t pev[13] = {};  // per-pass Gram / Cholesky / triangular-solve boundaries
     bool ev_ready = false;
     bool ev_pending = false;
     double stage_ms[ELMDDM_NUM_STAGES] = {};
-    double pass_ms[9] = {};   // per CholeskyQR pass: Gram, Cholesky + inverses, triangular solve
+    double pass_ms[12] = {};  // per CholeskyQR pass: Gram, Cholesky + inverses, triangular solve
     int timed_solves = 0;
 
     bool dry = false;   // size query only: count bytes, allocate nothing
@@ -152,10 +158,10 @@ struct elmddm_plan {
             return hipEventElapsedTime(&ms, a, b) == hipSuccess ? (double)ms : 0.0;
         };
         stage_ms[0] += el(ev[0], ev[1]);
-        for (int p = 0; p < 3; ++p) {
+        for (int p = 0; p < npass; ++p) {
             const double tg = el(pev[3 * p], pev[3 * p + 1]);
             const double tc = el(pev[3 * p + 1], pev[3 * p + 2]);
-            const double tt = el(pev[3 * p + 2], p < 2 ? pev[3 * p + 3] : pev[9]);
+            const double tt = el(pev[3 * p + 2], pev[3 * p + 3]);
             stage_ms[1] += tg;
             stage_ms[2] += tc;
             stage_ms[3] += tt;
@@ -163,7 +169,7 @@ struct elmddm_plan {
             pass_ms[3 * p + 1] += tc;
             pass_ms[3 * p + 2] += tt;
         }
-        stage_ms[3] += el(pev[9], ev[4]);
+        stage_ms[3] += el(pev[3 * npass], ev[4]);
         for (int i = 4; i < ELMDDM_NUM_STAGES; ++i) stage_ms[i] += el(ev[i], ev[i + 1]);
         ++timed_solves;
         ev_pending = false;
@@ -519,7 +525,7 @@ elmddm_status build(elmddm_plan* P)
     TRY(P->dalloc(&P->X0, NT * P->sX));
     TRY(P->dalloc(&P->X1, NT * P->sX));
     TRY(P->dalloc(&P->G, NT * P->sG));
-    for (int i = 0; i < 3; ++i) TRY(P->dalloc(&P->Linv[i], NT * P->sL));
+    for (int i = 0; i < P->npass; ++i) TRY(P->dalloc(&P->Linv[i], NT * P->sL));
     TRY(P->dalloc(&P->Dinv, NT * P->sD));
     TRY(P->dalloc(&P->Tbuf, NT * NB * n));
     TRY(P->dalloc(&P->P, NT * P->sP));
@@ -537,7 +543,7 @@ elmddm_status build(elmddm_plan* P)
     if (P->dry) return ELMDDM_OK;
     // The strictly upper parts of the inverse factors are never written by the
     // solve and must read as zero.
-    for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < P->npass; ++i)
         if (hipMemset(P->Linv[i], 0, NT * P->sL * sizeof(double)) != hipSuccess)
             return fail(ELMDDM_HIP_ERROR, "hipMemset failed during plan creation");
     // Entries of the interface factor outside the envelope are never written and read as zero.
@@ -604,6 +610,10 @@ elmddm_status elmddm_plan_create_batch(const elmddm_problem* problem, int32_t ba
     // one fused launch per envelope step is latency-optimal for few systems;
     // a separate panel + trailing GEMM wins once several systems share the launches
     P->env_fused = batch < 4;
+    // tanh feature blocks grow worse conditioned with the neuron count (at the
+    // configured scales: column-scaled kappa ~1e9 at n = 400, 1e12..1e13 at
+    // n = 800); one shifted pass covers kappa up to about 1e12, two beyond
+    P->npass = problem->neurons >= 600 ? 4 : 3;
     try {
         st = build(P);
     } catch (const std::bad_alloc&) {
@@ -627,6 +637,7 @@ elmddm_status elmddm_plan_query(const elmddm_problem* problem, int32_t batch, el
     elmddm_plan Q;
     Q.p = *problem;
     Q.B = batch;
+    Q.npass = problem->neurons >= 600 ? 4 : 3;
     Q.dry = true;
     try {
         st = build(&Q);
@@ -698,6 +709,23 @@ elmddm_status elmddm_plan_keep_schur(elmddm_plan* P, int32_t keep)
     return ELMDDM_OK;
 }
 
+elmddm_status elmddm_plan_set_passes(elmddm_plan* P, int32_t npass)
+{
+    if (!P) return fail(ELMDDM_INVALID_ARG, "NULL plan");
+    if (npass != 3 && npass != 4) return fail(ELMDDM_INVALID_ARG, "npass must be 3 or 4");
+    for (int i = 0; i < npass; ++i)
+        if (!P->Linv[i]) {
+            const size_t cnt = (size_t)P->NT * P->sL;
+            elmddm_status st = P->dalloc(&P->Linv[i], cnt);
+            if (st != ELMDDM_OK) return st;
+            if (hipMemset(P->Linv[i], 0, cnt * sizeof(double)) != hipSuccess)
+                return fail(ELMDDM_HIP_ERROR, "hipMemset failed");
+        }
+    P->npass = npass;
+    P->factors_valid = false;
+    return ELMDDM_OK;
+}
+
 elmddm_status elmddm_plan_set_mode(elmddm_plan* P, int32_t mode)
 {
     if (!P) return fail(ELMDDM_INVALID_ARG, "NULL plan");
@@ -741,6 +769,12 @@ elmddm_status elmddm_solve(elmddm_plan* P, const double* W, const double* b, con
     // Feature assembly: X0 = [K rows | interface rows | flux rows], column n = F.
     assemble(st, N, P->N, P->nB, ldx, n, row_table(P), sub_geom(P), P->p.op, W, b, f, g, coef, P->q2,
              P->X0, nullptr, 0, nullptr, 0, nullptr, 0);
+    // the last pass reads X1 when the pass count is even: give it the F column too
+    if (P->npass % 2 == 0 &&
+        hipMemcpy2DAsync(P->X1 + (size_t)n * ldx, P->sX * sizeof(double), P->X0 + (size_t)n * ldx,
+                         P->sX * sizeof(double), (size_t)ldx * sizeof(double), N, hipMemcpyDeviceToDevice,
+                         st) != hipSuccess)
+        return check_launch("F column copy");
     P->mark(1, st);
 
     // Three-pass shifted CholeskyQR of every K^s (Fukaya et al., SIAM J. Sci.
@@ -753,30 +787,34 @@ elmddm_status elmddm_solve(elmddm_plan* P, const double* W, const double* b, con
     // FP64: the bound of Fukaya et al. for column-scaled X; mixed: a shift that
     // covers the FP32 rounding of the pass-1 Gram entries (errors of order
     // sqrt(m) u32 relative to |k_i||k_j|, spectral norm a few sqrt(n) times that).
-    const double shift = mixed ? 16.0 * std::sqrt((double)P->gram_rows * n) * 0x1p-24
-                               : 11.0 * ((double)P->gram_rows * n + (double)n * (n + 1)) * u * n;
+    const double shift64 = 11.0 * ((double)P->gram_rows * n + (double)n * (n + 1)) * u * n;
+    const double shift32 = 16.0 * std::sqrt((double)P->gram_rows * n) * 0x1p-24;
     double* src = P->X0;
     double* dst = P->X1;
-    for (int pass = 1; pass <= 3; ++pass) {
-        const int ncol = pass == 3 ? n + 1 : n;
+    const int np = P->npass;
+    for (int pass = 1; pass <= np; ++pass) {
+        const bool last = pass == np;
+        const int ncol = last ? n + 1 : n;
         if (P->timing) (void)hipEventRecord(P->pev[3 * (pass - 1)], st);
         if (pass == 1 && mixed)
             gram_product_f32(st, n, P->gram_rows, src, ldx, P->sX, P->G, ldg, P->sG, N);
         else
             gram_product(st, P->gram_code, n, P->gram_rows, src, ldx, P->sX, P->G, ldg, P->sG, N);
         if (P->timing) (void)hipEventRecord(P->pev[3 * (pass - 1) + 1], st);
-        if (pass == 3) gram_rhs_row(st, src, ldx, P->sX, P->gram_rows, n, P->G, ldg, P->sG, N);
-        if (pass == 1) scale_diag(st, P->G, ldg, P->sG, n, 1.0 + shift, N);
+        if (last) gram_rhs_row(st, src, ldx, P->sX, P->gram_rows, n, P->G, ldg, P->sG, N);
+        if (pass <= np - 2) scale_diag(st, P->G, ldg, P->sG, n, 1.0 + (pass == 1 && mixed ? shift32 : shift64), N);
         blocked_potrf(st, P->G, ldg, P->sG, ncol, n, P->Dinv, P->sD, P->Linv[pass - 1], ldg, P->sL,
                       P->Tbuf, P->d_info, pass, N, P->dsave, n);
         if (P->timing) (void)hipEventRecord(P->pev[3 * (pass - 1) + 2], st);
-        const int r0 = pass == 3 ? P->mI : 0;
+        const int r0 = last ? P->mI : 0;
         trsm_product(st, P->trsm_code, ldx - r0, n, src + r0, ldx, P->sX, P->Linv[pass - 1], ldg, P->sL,
                      dst + r0, P->sX, N);
-        if (pass < 3) std::swap(src, dst);
+        if (!last) std::swap(src, dst);
     }
-    if (P->timing) (void)hipEventRecord(P->pev[9], st);
-    // dst (X1) now holds Q3 interface rows and Z^T = A R^{-1}; put h^T in its row.
+    if (P->timing) (void)hipEventRecord(P->pev[3 * np], st);
+    P->Qprev = src;
+    P->Xfin = dst;
+    // dst now holds the last pass's interface rows and Z^T = A R^{-1}; put h^T in its row.
     copy_row(st, P->G + n, ldg, P->sG, dst + P->hrow, ldx, P->sX, n, N);
     P->mark(4, st);
     elmddm_status est = check_launch("local factorisation");
@@ -824,7 +862,7 @@ elmddm_status elmddm_solve(elmddm_plan* P, const double* W, const double* b, con
     }
     P->mark(7, st);
     local_backsolve(st, N, P->N, P->nG, n, P->kpad, dst, ldx, P->sX, P->mI, P->hrow, P->d_gidx, u_gamma,
-                    P->Linv[0], P->Linv[1], P->Linv[2], ldg, P->sL, c, P->bs1, P->bs2);
+                    P->Linv, np, ldg, P->sL, c, P->bs1, P->bs2);
     const long long nc = (long long)N * n;
     P->mark(8, st);
     check_finite(st, c, nc, P->d_info);
@@ -894,13 +932,13 @@ void rhs_stage(elmddm_plan* P, hipStream_t st, int R, const double* f, const dou
     // after a solve: X0 = Q2 (all rows), X1 rows [mI, ldx) = Q3 interface rows, h row, Z^T rows
     rhs_assemble(st, row_table(P), ldx, P->gram_rows, ldf, f, g, N, R, nf, P->nB, P->Fr);
     // h = L3^{-1} Q2^T F
-    gemm_f64(st, true, false, 0, false, n, R, P->gram_rows, 1.0, P->X0, ldx, P->sX, P->Fr, ldf, (long long)R * ldf,
+    gemm_f64(st, true, false, 0, false, n, R, P->gram_rows, 1.0, P->Qprev, ldx, P->sX, P->Fr, ldf, (long long)R * ldf,
              0.0, P->Tm, n, (long long)R * n, N);
-    gemm_f64(st, false, false, 0, false, n, R, n, 1.0, P->Linv[2], ldg, P->sL, P->Tm, n, (long long)R * n, 0.0,
-             P->Hm, n, (long long)R * n, N);
+    gemm_f64(st, false, false, 0, false, n, R, n, 1.0, P->Linv[P->npass - 1], ldg, P->sL, P->Tm, n,
+             (long long)R * n, 0.0, P->Hm, n, (long long)R * n, N);
     if (nG == 0) return;
     // [q; a] = [Q_Gamma^T h; Z h] per subdomain, laid out [rhs][subdomain][ldp]
-    gemm_f64(st, false, false, 0, false, 2 * kp + 16, R, n, 1.0, P->X1 + P->mI, ldx, P->sX, P->Hm, n,
+    gemm_f64(st, false, false, 0, false, 2 * kp + 16, R, n, 1.0, P->Xfin + P->mI, ldx, P->sX, P->Hm, n,
              (long long)R * n, 0.0, P->Ph, N * ldp, ldp, N);
     schur_avec(st, P->nE, P->d_adesc, P->Ph, ldp, ldp, kp + 16, 0, mg, P->abufR, N, R);
     schur_rhs(st, P->nE, mg, P->d_qdesc, P->d_gptr, P->d_gdesc, P->Ph, ldp, ldp, 0, P->Mbuf, P->abufR, P->yR, 1,
@@ -937,15 +975,17 @@ elmddm_status elmddm_solve_rhs(elmddm_plan* P, int32_t nrhs, const double* f, co
             unpermute(st, P->nE, mg, P->d_perm, P->uR, u_gamma + (long long)r0 * nG, R);
         }
         if (c) {
-            // c = Linv1^T Linv2^T Linv3^T (h + Q_Gamma^T u)
-            backsolve_rhs_multi(st, N, n, kp, P->X1, ldx, P->sX, P->mI, P->d_gidx,
+            // c = Linv1^T ... Linv_npass^T (h + Q_Gamma^T u)
+            backsolve_rhs_multi(st, N, n, kp, P->Xfin, ldx, P->sX, P->mI, P->d_gidx,
                                 nG > 0 ? u_gamma + (long long)r0 * nG : nullptr, nG, P->Hm, P->Vm, R);
-            gemm_f64(st, true, false, 0, false, n, R, n, 1.0, P->Linv[2], ldg, P->sL, P->Vm, n, (long long)R * n,
-                     0.0, P->Tm, n, (long long)R * n, N);
-            gemm_f64(st, true, false, 0, false, n, R, n, 1.0, P->Linv[1], ldg, P->sL, P->Tm, n, (long long)R * n,
-                     0.0, P->Vm, n, (long long)R * n, N);
-            gemm_f64(st, true, false, 0, false, n, R, n, 1.0, P->Linv[0], ldg, P->sL, P->Vm, n, (long long)R * n,
-                     0.0, c + (long long)r0 * N * n, N * n, n, N);
+            double* cur = P->Vm;
+            double* nxt = P->Tm;
+            for (int q = P->npass - 1; q >= 0; --q) {
+                double* out = q == 0 ? c + (long long)r0 * N * n : nxt;
+                gemm_f64(st, true, false, 0, false, n, R, n, 1.0, P->Linv[q], ldg, P->sL, cur, n, (long long)R * n,
+                         0.0, out, q == 0 ? N * n : n, q == 0 ? (long long)n : (long long)R * n, N);
+                std::swap(cur, nxt);
+            }
         }
     }
     return check_launch("solve_rhs");
@@ -1137,7 +1177,7 @@ elmddm_status elmddm_pass_times(elmddm_plan* P, double* ms, int32_t* solves)
 {
     if (!P || !ms) return fail(ELMDDM_INVALID_ARG, "NULL argument");
     P->harvest();
-    for (int i = 0; i < 9; ++i) ms[i] = P->pass_ms[i];
+    for (int i = 0; i < 12; ++i) ms[i] = i < 3 * P->npass ? P->pass_ms[i] : 0.0;
     if (solves) *solves = P->timed_solves;
     return ELMDDM_OK;
 }

@@ -236,3 +236,36 @@ def test_autotuned_kernels_and_split_envelope_path_match_oracle(gpu):
     for i in (0, 3):
         o = ddm.solve(P, Ws[i], bs[i], data, lay)
         assert rel(U[i], o.u_gamma) <= TOL_FP64
+
+
+@pytest.mark.parametrize("mode,tol", [(0, TOL_FP64), (1, 1e-6)])
+def test_four_pass_factorisation_matches_oracle(gpu, mode, tol):
+    """Two shifted CholeskyQR passes (forced on a small case) give the same answer."""
+    from paper_2406_15959_amd import binding as B
+    P = wl.Problem(4, 3, 130, 13, 12, 12, 17, R=2.5)
+    plan = B.Plan(to_c_problem(P))
+    plan.set_passes(4)
+    plan.set_mode(mode)
+    g = gpu_solve(P, 9, plan=plan)
+    o = oracle_solve(P, 9)
+    assert g["info"].status == 0
+    assert rel(g["u_gamma"], o["u_gamma"]) <= tol
+    assert rel(g["uh"], o["uh"]) <= tol
+    with pytest.raises(B.ElmddmError):
+        plan.set_passes(5)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("mode,tol", [(0, TOL_FP64), (1, 1e-6)])
+def test_800_neuron_variable_coefficient_problem_matches_oracle(gpu, mode, tol):
+    """A ragged-batch shape with badly conditioned blocks (4x4 subdomains,
+    800 neurons, column-scaled kappa(K_s) up to ~1e13): four passes by default."""
+    from paper_2406_15959_amd import binding as B
+    P = [p for p in wl.ragged_problems(64) if p.neurons == 800 and p.nsub_x == 4][0]
+    plan = B.Plan(to_c_problem(P))
+    plan.set_mode(mode)
+    g = gpu_solve(P, 77, plan=plan, eval_per_sub=8)
+    o = oracle_solve(P, 77, eval_per_sub=8)
+    assert g["info"].status == 0, (g["info"].status, g["info"].bad_pass)
+    assert rel(g["u_gamma"], o["u_gamma"]) <= tol
+    assert rel(g["uh"], o["uh"]) <= tol

@@ -29,11 +29,15 @@ def oracle_fourier(P, seed, alpha):
     return sol.u_gamma, ddm.evaluate(P, lay, W, b, sol.c, ex, ey)
 
 
-def run_rhs(P, seed, alphas, reserve):
+def run_rhs(P, seed, alphas, reserve, npass=None):
     import torch
     from paper_2406_15959_amd import binding as B
     dev = torch.device("cuda:0")
-    g0 = gpu_solve(P, seed)                       # factors of this hidden layer
+    plan = None
+    if npass:
+        plan = B.Plan(to_c_problem(P))
+        plan.set_passes(npass)
+    g0 = gpu_solve(P, seed, plan=plan)            # factors of this hidden layer
     plan = g0["plan"]
     assert g0["info"].status == 0
     s = plan.sizes
@@ -58,14 +62,15 @@ def run_rhs(P, seed, alphas, reserve):
     return out
 
 
-@pytest.mark.parametrize("P,seed,R,reserve", [
-    (wl.Problem(4, 3, 130, 13, 12, 12, 17, R=2.5), 9, 5, 2),
-    (wl.Problem(3, 3, 60, 10, 10, 8, 6, R=2.0), 21, 3, 8),
-    (wl.Problem(1, 1, 90, 12, 12, 11, 4, R=2.0), 8, 2, 1),
+@pytest.mark.parametrize("P,seed,R,reserve,npass", [
+    (wl.Problem(4, 3, 130, 13, 12, 12, 17, R=2.5), 9, 5, 2, None),
+    (wl.Problem(3, 3, 60, 10, 10, 8, 6, R=2.0), 21, 3, 8, None),
+    (wl.Problem(1, 1, 90, 12, 12, 11, 4, R=2.0), 8, 2, 1, None),
+    (wl.Problem(3, 3, 60, 10, 10, 8, 6, R=2.0), 22, 3, 2, 4),
 ])
-def test_further_rhs_match_oracle(gpu, P, seed, R, reserve):
+def test_further_rhs_match_oracle(gpu, P, seed, R, reserve, npass):
     alphas = wl.fourier_coeffs(77 + seed, modes=6, count=R)
-    got = run_rhs(P, seed, alphas, reserve)
+    got = run_rhs(P, seed, alphas, reserve, npass)
     for r in range(R):
         ug, uo = oracle_fourier(P, seed, alphas[r])
         if P.n_interface:
