@@ -174,7 +174,7 @@ def learned_leg(B, wl, torch, log):
     return out
 
 
-def ragged_leg(B, wl, torch, log, count=256, budget=150e9, launches=2):
+def ragged_leg(B, wl, torch, log, count=256, budget=150e9, launches=2, mode=None):
     """Ragged batch: `count` independent variable-coefficient problems of
     mixed shapes (subdomain grid 4x4 / 8x8 / 16x16, 100-800 neurons), one
     batched plan per shape (mixed precision, autotuned kernels), all solves
@@ -182,7 +182,8 @@ def ragged_leg(B, wl, torch, log, count=256, budget=150e9, launches=2):
     from paper_2406_15959_amd import ragged
     probs = wl.ragged_problems(count)
     t0 = time.perf_counter()
-    rb = ragged.RaggedBatch(probs, budget_bytes=budget, mode=B.MODE_MIXED)
+    mode = B.MODE_FP64 if mode is None else mode
+    rb = ragged.RaggedBatch(probs, budget_bytes=budget, mode=mode)
     setup_plans = time.perf_counter() - t0
     dev = torch.device("cuda:0")
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
@@ -201,11 +202,17 @@ def ragged_leg(B, wl, torch, log, count=256, budget=150e9, launches=2):
         rb.launch()
     torch.cuda.synchronize()
     el = (time.perf_counter() - t0) / launches
-    statuses = [rb.result(i)[2].status for i in range(count)]
+    infos = [rb.result(i)[2] for i in range(count)]
+    statuses = [inf.status for inf in infos]
+    failed = [{"problem": i, "grid": probs[i].nsub_x, "neurons": probs[i].neurons, "k1": probs[i].k1,
+               "k2": probs[i].k2, "status": int(inf.status), "pass": int(inf.bad_pass),
+               "subdomain": int(inf.bad_subdomain)} for i, inf in enumerate(infos) if inf.status != 0]
     # accuracy against the manufactured solution for every problem; parity
     # against the oracle for a sample of the smallest shapes
     errs = []
     for i, P in enumerate(probs):
+        if statuses[i] != 0:
+            continue
         u, c, _ = rb.result(i)
         ex, ey = wl.eval_grid(P, 8)
         uh = torch.zeros(len(ex), dtype=torch.float64, device=dev)
@@ -226,10 +233,10 @@ def ragged_leg(B, wl, torch, log, count=256, budget=150e9, launches=2):
                     "rel_l2_u_gamma_vs_oracle": float(np.linalg.norm(u - sol.u_gamma) / np.linalg.norm(sol.u_gamma))})
     return {"workload": "%d variable-coefficient problems -div(a grad u) = f, a = 1 + sin(2 pi k1 x) cos(2 pi k2 y) / 2, "
                         "grids {4x4, 8x8, 16x16}, neurons {100, 200, 400, 800}, q = round(2 sqrt(n)) points per "
-                        "direction and edge; mixed precision" % count,
+                        "direction and edge; %s" % (count, "FP64" if mode == B.MODE_FP64 else "mixed precision"),
             "problems": count, "shapes": len(rb.shapes), "solves_per_graph_launch": sum(len(sh["chunks"]) for sh in rb.shapes),
             "graph_launch_ms": 1e3 * el, "problems_per_s": count / el,
-            "all_ok": all(st == 0 for st in statuses),
+            "all_ok": all(st == 0 for st in statuses), "failed": failed,
             "rel_l2_uh_vs_exact_median": float(np.median(errs)), "rel_l2_uh_vs_exact_max": float(np.max(errs)),
             "parity_sample": par, "plan_setup_s": setup_plans,
             "plans": [{"grid": sh["key"][0], "neurons": sh["key"][2], "batch": sh["batch"],
@@ -302,8 +309,10 @@ def main():
             W, b = inst[i % len(inst)]
             plan.solve(W, b, df, dg, None, du, dc)
         torch.cuda.synchronize()
-        if plan.solve_info().status != 0:
-            raise SystemExit(f"warmup solve failed with status {plan.solve_info().status}")
+        inf = plan.solve_info()
+        if inf.status != 0:
+            raise SystemExit(f"warmup solve failed with status {inf.status} (pass {inf.bad_pass}, "
+                             f"subdomain {inf.bad_subdomain}, instance {inf.bad_instance}, kernels {tuned})")
         plan.set_timing(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -315,6 +324,14 @@ def main():
         stage_ms, nsolved = plan.stage_times()
         pass_ms, _ = plan.pass_times()
         plan.set_timing(False)
+        # the timed solves are deterministic: re-solve each batch once to read its status
+        bad = []
+        for k, (W, b) in enumerate(inst):
+            plan.solve(W, b, df, dg, None, du, dc)
+            inf = plan.solve_info()
+            if inf.status != 0:
+                bad.append({"batch": k, "status": int(inf.status), "pass": int(inf.bad_pass),
+                            "subdomain": int(inf.bad_subdomain), "instance": int(inf.bad_instance)})
         # instance 0 of the batch (its slices of W, b, c are the leading ones), for parity
         plan.solve(W0, b0, df, dg, None, du, dc)
         info = plan.solve_info()
@@ -322,7 +339,7 @@ def main():
         torch.cuda.synchronize()
         k = max(nsolved, 1)
         return {"elapsed": t1 - t0, "stage_ms": [v / k for v in stage_ms],
-                "pass_ms": [[v / k for v in row] for row in pass_ms], "status": int(info.status),
+                "pass_ms": [[v / k for v in row] for row in pass_ms], "status": int(info.status), "failed": bad,
                 "u": du[:s.n_interface].cpu().numpy(), "uh": uh.cpu().numpy()}
 
     runs = {"fp64": run_mode(B.MODE_FP64), "mixed": run_mode(B.MODE_MIXED)}
@@ -352,16 +369,16 @@ def main():
     tol = {"fp64": 1e-8, "mixed": 1e-6}
     modes = {}
     for name, r in runs.items():
-        par = {"status": r["status"],
+        par = {"status": r["status"], "timed_batches_failed": r["failed"],
                "rel_l2_vs_exact_uh": float(np.linalg.norm(r["uh"] - u_exact) / np.linalg.norm(u_exact)),
                "tolerance": tol[name]}
         if oracle_ref is not None:
             par["rel_l2_u_gamma_vs_oracle"] = float(np.linalg.norm(r["u"] - oracle_ref[0]) / np.linalg.norm(oracle_ref[0]))
             par["rel_l2_uh_vs_oracle"] = float(np.linalg.norm(r["uh"] - oracle_ref[1]) / np.linalg.norm(oracle_ref[1]))
-            par["ok"] = bool(r["status"] == 0 and par["rel_l2_u_gamma_vs_oracle"] <= tol[name]
+            par["ok"] = bool(r["status"] == 0 and not r["failed"] and par["rel_l2_u_gamma_vs_oracle"] <= tol[name]
                              and par["rel_l2_uh_vs_oracle"] <= tol[name])
         else:
-            par["ok"] = r["status"] == 0
+            par["ok"] = r["status"] == 0 and not r["failed"]
         v = args.steps * nb / r["elapsed"]
         modes[name] = {"value": v if par["ok"] else 0.0, "ms_per_step": 1e3 * r["elapsed"] / args.steps,
                        "parity": par,

@@ -263,6 +263,10 @@ elmddm_status elmddm_plan_set_mode(elmddm_plan* plan, int32_t mode);
  * strip width T. */
 elmddm_status elmddm_autotune(elmddm_plan* plan, void* stream, int32_t* choice);
 
+/* Choose the kernels of the two large local products by code (as reported
+ * by elmddm_autotune) instead of tuning. */
+elmddm_status elmddm_plan_set_kernels(elmddm_plan* plan, int32_t gram_code, int32_t trsm_code);
+
 /* Candidate timings of the last elmddm_autotune (zeros before one): codes
  * [9] receives the kernel codes, gram_ms [9] and trsm_ms [9] the time of
  * one Gram product and one triangular solve over the whole batch with each

@@ -35,7 +35,7 @@ EXPORTED = [
     "elmddm_plan_create", "elmddm_plan_create_batch", "elmddm_plan_destroy", "elmddm_plan_sizes", "elmddm_points",
     "elmddm_solve", "elmddm_solve_info", "elmddm_eval", "elmddm_assemble",
     "elmddm_plan_keep_schur", "elmddm_get_schur", "elmddm_set_timing", "elmddm_stage_times", "elmddm_pass_times",
-    "elmddm_autotune", "elmddm_autotune_times", "elmddm_plan_set_mode", "elmddm_plan_set_passes", "elmddm_plan_reserve_rhs", "elmddm_solve_rhs",
+    "elmddm_autotune", "elmddm_autotune_times", "elmddm_plan_set_kernels", "elmddm_plan_set_mode", "elmddm_plan_set_passes", "elmddm_plan_reserve_rhs", "elmddm_solve_rhs",
     "elmddm_schur_rhs", "elmddm_interface_cg",
     "elmddm_mlp_create", "elmddm_mlp_destroy", "elmddm_mlp_num_params", "elmddm_mlp_set_params",
     "elmddm_mlp_get_params", "elmddm_mlp_forward", "elmddm_mlp_loss_grad", "elmddm_mlp_adam_step",
@@ -106,6 +106,7 @@ def lib():
         L.elmddm_autotune.argtypes = [vp, vp, ctypes.POINTER(i32)]
         L.elmddm_plan_set_mode.argtypes = [vp, i32]
         L.elmddm_plan_set_passes.argtypes = [vp, i32]
+        L.elmddm_plan_set_kernels.argtypes = [vp, i32, i32]
         L.elmddm_autotune_times.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double),
                                             ctypes.POINTER(ctypes.c_double)]
         L.elmddm_plan_reserve_rhs.argtypes = [vp, i32]
@@ -281,6 +282,9 @@ class Plan:
         n = ctypes.c_int32()
         _check(lib().elmddm_pass_times(self._h, ms, ctypes.byref(n)))
         return [list(ms[3 * p:3 * p + 3]) for p in range(4)], n.value
+
+    def set_kernels(self, gram_code, trsm_code):
+        _check(lib().elmddm_plan_set_kernels(self._h, gram_code, trsm_code))
 
     def set_passes(self, npass):
         _check(lib().elmddm_plan_set_passes(self._h, npass))

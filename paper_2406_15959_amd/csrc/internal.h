@@ -157,7 +157,8 @@ constexpr int NB = 64;  // block size of the blocked Cholesky
 // (saved into dsave, stride sS per matrix) is reported through info.
 void blocked_potrf(hipStream_t st, double* A, int lda, long long sA, int Mrows, int n, double* Dinv,
                    long long sD, double* Linv, int ldl, long long sL, double* Tbuf, DevInfo* info,
-                   int pass, int batch, double* dsave, long long sS);
+                   int pass, int batch, double* dsave, long long sS,
+                   double tau = -1.0);
 
 // Cholesky of one n x n SPD matrix whose nonzeros lie inside a column
 // envelope: rend[p] = one past the last row that may be nonzero in the

@@ -11,9 +11,9 @@ namespace elmddm {
 // the full inverse factor L^{-1} (strictly upper part left untouched).
 void blocked_potrf(hipStream_t st, double* A, int lda, long long sA, int Mrows, int n, double* Dinv,
                    long long sD, double* Linv, int ldl, long long sL, double* Tbuf, DevInfo* info,
-                   int pass, int batch, double* dsave, long long sS)
+                   int pass, int batch, double* dsave, long long sS, double tau)
 {
-    const double tau = 64.0 * n * 0x1p-53;
+    if (tau < 0.0) tau = 64.0 * n * 0x1p-53;
     if (dsave) save_diag(st, A, lda, sA, n, dsave, sS, batch);
     for (int j = 0; j < n; j += NB) {
         const int jb = std::min(NB, n - j);

@@ -803,8 +803,14 @@ elmddm_status elmddm_solve(elmddm_plan* P, const double* W, const double* b, con
         if (P->timing) (void)hipEventRecord(P->pev[3 * (pass - 1) + 1], st);
         if (last) gram_rhs_row(st, src, ldx, P->sX, P->gram_rows, n, P->G, ldg, P->sG, N);
         if (pass <= np - 2) scale_diag(st, P->G, ldg, P->sG, n, 1.0 + (pass == 1 && mixed ? shift32 : shift64), N);
+        // breakdown threshold on pivot / original diagonal: 64 n u, except for
+        // the unshifted middle pass of the mixed mode, whose input has
+        // kappa(Q1) up to ~1e8 after the larger FP32 shift and legitimately
+        // meets pivots down to ~1e-12 of the diagonal; there only pivots at
+        // the rounding level (<= 64 u, e.g. from duplicate neurons) are flagged
+        const double tau = (mixed && !last && pass > np - 2) ? 64.0 * u : 64.0 * n * u;
         blocked_potrf(st, P->G, ldg, P->sG, ncol, n, P->Dinv, P->sD, P->Linv[pass - 1], ldg, P->sL,
-                      P->Tbuf, P->d_info, pass, N, P->dsave, n);
+                      P->Tbuf, P->d_info, pass, N, P->dsave, n, tau);
         if (P->timing) (void)hipEventRecord(P->pev[3 * (pass - 1) + 2], st);
         const int r0 = last ? P->mI : 0;
         trsm_product(st, P->trsm_code, ldx - r0, n, src + r0, ldx, P->sX, P->Linv[pass - 1], ldg, P->sL,
@@ -1158,6 +1164,16 @@ elmddm_status elmddm_stage_times(elmddm_plan* P, double* ms, int32_t* solves)
     P->harvest();
     for (int i = 0; i < ELMDDM_NUM_STAGES; ++i) ms[i] = P->stage_ms[i];
     if (solves) *solves = P->timed_solves;
+    return ELMDDM_OK;
+}
+
+elmddm_status elmddm_plan_set_kernels(elmddm_plan* P, int32_t gram_code, int32_t trsm_code)
+{
+    if (!P) return fail(ELMDDM_INVALID_ARG, "NULL plan");
+    auto ok = [](int c) { return (c >= -4 && c <= -1) || (c >= 4 && c <= 8); };
+    if (!ok(gram_code) || !ok(trsm_code)) return fail(ELMDDM_INVALID_ARG, "kernel code out of range");
+    P->gram_code = gram_code;
+    P->trsm_code = trsm_code;
     return ELMDDM_OK;
 }
 

@@ -65,3 +65,15 @@ def test_mode_switch_is_validated_and_reversible(gpu):
     g1 = gpu_solve(P, 1000, plan=plan)
     g2 = gpu_solve(P, 1000)
     assert np.array_equal(g1["u_gamma"], g2["u_gamma"])
+
+
+def test_mixed_8x8_badly_conditioned_instance(gpu):
+    """Hidden-layer seed 2009 has a block with column-scaled kappa 4e9: the
+    FP32-shifted first pass leaves kappa(Q1) ~ 1e7 and pass-2 pivots near
+    3e-12 of the diagonal, legitimate for an unshifted middle pass."""
+    P = wl.CONFIG_8x8
+    gm = gpu_solve(P, 2009, plan=mixed_plan(P))
+    o = oracle_solve(P, 2009)
+    assert gm["info"].status == 0, (gm["info"].bad_pass, gm["info"].bad_subdomain)
+    assert rel(gm["u_gamma"], o["u_gamma"]) <= TOL_MIXED
+    assert rel(gm["uh"], o["uh"]) <= TOL_MIXED

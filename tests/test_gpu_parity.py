@@ -98,12 +98,15 @@ def test_full_8x8_matches_oracle(gpu):
     assert rel(g["uh"], wl.exact_u(P, ex, ey)) < 1e-4
 
 
-def test_duplicate_neurons_report_not_spd(gpu):
-    """Two identical neurons make K^s rank deficient: reported with the subdomain index."""
+@pytest.mark.parametrize("mode", [0, 1])
+def test_duplicate_neurons_report_not_spd(gpu, mode):
+    """Two identical neurons make K^s rank deficient: reported with the subdomain index
+    (in both precision modes)."""
     import torch
     from paper_2406_15959_amd import binding as B
     P = wl.Problem(2, 2, 40, 8, 8, 6, 6, R=2.0)
     plan = B.Plan(to_c_problem(P))
+    plan.set_mode(mode)
     s = plan.sizes
     W, b = wl.hidden_params(P, 4)
     W[2, 5] = W[2, 3]
