@@ -36,7 +36,8 @@ PMC_SUMMARY = os.path.join(ROOT, "profiles", "gram_8x8_fp64_batch8_pmc.txt")
 
 def measured_traffic(gram_code, batch):
     """HBM bytes per Gram launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
-    summary, if it was taken with this kernel source, kernel choice and batch; else None."""
+    summary (one entry per autotuner candidate), if it was taken with this kernel
+    source and batch; else None."""
     import hashlib
     try:
         kv = {}
@@ -46,9 +47,9 @@ def measured_traffic(gram_code, batch):
                 kv[k.strip()] = v.strip()
         src = os.path.join(ROOT, "paper_2406_15959_amd", "csrc", "kernels.hip")
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        if kv.get("kernels_hip_sha256") != sha or int(kv["gram_code"]) != gram_code or int(kv["batch"]) != batch:
+        if kv.get("kernels_hip_sha256") != sha or int(kv["batch"]) != batch:
             return None
-        return float(kv["traffic_bytes_per_launch"])
+        return float(kv["traffic_bytes_per_launch[%d]" % gram_code])
     except (OSError, KeyError, ValueError):
         return None
 
