@@ -68,6 +68,9 @@ typedef enum elmddm_status {
 
 enum { ELMDDM_OP_POISSON = 0, ELMDDM_OP_VARCOEF = 1 };
 
+/* Plan flags (elmddm_plan_create_ex). */
+enum { ELMDDM_PLAN_MATRIX_FREE = 1, ELMDDM_PLAN_DENSE = 2 };
+
 /* Precision modes (see elmddm_plan_set_mode). */
 enum { ELMDDM_MODE_FP64 = 0, ELMDDM_MODE_MIXED = 1 };
 
@@ -106,7 +109,7 @@ typedef struct elmddm_sizes {
 typedef struct elmddm_info {
     int32_t status;          /* elmddm_status of the last solve                 */
     int32_t bad_subdomain;   /* first subdomain whose local factorisation failed, else -1 */
-    int32_t bad_pass;        /* CholeskyQR pass (1..4) of that failure, else 0  */
+    int32_t bad_pass;        /* CholeskyQR pass (1..5) of that failure, else 0  */
     int32_t bad_instance;    /* problem instance of that failure, else -1       */
 } elmddm_info;
 
@@ -129,6 +132,33 @@ elmddm_status elmddm_plan_create(const elmddm_problem* problem, elmddm_plan** pl
  * returns instance 0. */
 elmddm_status elmddm_plan_create_batch(const elmddm_problem* problem, int32_t batch,
                                        elmddm_plan** plan);
+
+/* As elmddm_plan_create_batch, with the interface-solver choice:
+ *  ELMDDM_PLAN_DENSE: S is formed and factored (envelope Cholesky, exact);
+ *  ELMDDM_PLAN_MATRIX_FREE: S is never formed; the interface system is solved
+ *    by CG (the paper's interface solver, Section 3) with S v applied from
+ *    the per-subdomain blocks T_s = Y_s^T Y_s and the nonzero blocks of M
+ *    (memory O(sum_s k_s^2) instead of O(nG^2)).  elmddm_solve then runs CG
+ *    to ||g - S u|| <= tol ||g|| (elmddm_plan_set_cg; default tol 1e-12,
+ *    100000 iterations) and synchronises the stream while it polls the
+ *    convergence flags every 32 iterations; NOT_CONVERGED is reported by
+ *    elmddm_solve_info.  Matrix-free plans cannot be captured into graphs and
+ *    keep no S.
+ *  0: dense unless the three nG x nG arrays of the dense path would exceed
+ *    64 GB (the 32 x 32 case with 64 points per edge needs 387 GB). */
+elmddm_status elmddm_plan_create_ex(const elmddm_problem* problem, int32_t batch, uint32_t flags,
+                                    elmddm_plan** plan);
+
+/* 1 if the plan solves the interface system matrix-free, else 0. */
+int32_t elmddm_plan_is_matrix_free(const elmddm_plan* plan);
+
+/* CG stopping rule of matrix-free plans: ||g - S u|| <= tol ||g|| (0 < tol < 1),
+ * at most maxit iterations. */
+elmddm_status elmddm_plan_set_cg(elmddm_plan* plan, double tol, int32_t maxit);
+
+/* Iterations and final relative residuals (recurrence) of the last CG run on a
+ * matrix-free plan, per instance (host arrays of batch entries). */
+elmddm_status elmddm_plan_cg_stats(const elmddm_plan* plan, int32_t* iters, double* relres);
 
 /* Sizes (including device_bytes) that elmddm_plan_create_batch would give,
  * computed on the host without allocating anything. */
@@ -228,12 +258,13 @@ elmddm_status elmddm_schur_rhs(elmddm_plan* plan, int32_t nrhs, const double* f,
 elmddm_status elmddm_interface_cg(elmddm_plan* plan, int32_t nrhs, const double* rhs, double* u, double tol,
                                   int32_t maxit, int32_t* iters, double* relres, void* stream);
 
-/* Number of CholeskyQR passes of the local least squares (3 or 4; passes
+/* Number of CholeskyQR passes of the local least squares (3 to 5; passes
  * 1 .. npass - 2 carry the diagonal shift, the last one also yields h).  One
  * shifted pass handles column-scaled condition numbers of K^s up to about
- * 1e12, two up to about 1e15.  Default: 4 for neurons >= 600, else 3 (the
- * tanh feature blocks of the configured scales reach 1e12..1e13 at 800
- * neurons).  Allocates a fourth inverse factor on first use. */
+ * 1e12, two up to about 1e14, three up to about 1e16.  Default: 5 for neurons
+ * >= 900, 4 for neurons >= 600, else 3 (the tanh feature blocks of the
+ * configured scales reach 1e12..1e13 at 800 and ~1e15 at 1000 neurons).
+ * Allocates further inverse factors on first use. */
 elmddm_status elmddm_plan_set_passes(elmddm_plan* plan, int32_t npass);
 
 /* Precision mode of later solves on this plan.
@@ -290,8 +321,8 @@ elmddm_status elmddm_stage_times(elmddm_plan* plan, double* ms, int32_t* solves)
 /* The local-factorisation stages split by CholeskyQR pass (same timing
  * switch and totals as elmddm_stage_times): ms[3 p + 0] Gram product,
  * ms[3 p + 1] Cholesky + inverses, ms[3 p + 2] triangular solve of pass
- * p + 1 (p = 0 .. 3; zeros beyond the plan's pass count), in milliseconds
- * summed over the timed solves.  ms holds 12 doubles. */
+ * p + 1 (p = 0 .. 4; zeros beyond the plan's pass count), in milliseconds
+ * summed over the timed solves.  ms holds 15 doubles. */
 elmddm_status elmddm_pass_times(elmddm_plan* plan, double* ms, int32_t* solves);
 
 /* ------------------------------------------------------------------------

@@ -30,6 +30,8 @@ POINTS_BOUNDARY = 1
 POINTS_INTERFACE = 2
 MODE_FP64 = 0
 MODE_MIXED = 1
+PLAN_MATRIX_FREE = 1
+PLAN_DENSE = 2
 
 EXPORTED = [
     "elmddm_plan_create", "elmddm_plan_create_batch", "elmddm_plan_destroy", "elmddm_plan_sizes", "elmddm_points",
@@ -40,7 +42,8 @@ EXPORTED = [
     "elmddm_mlp_create", "elmddm_mlp_destroy", "elmddm_mlp_num_params", "elmddm_mlp_set_params",
     "elmddm_mlp_get_params", "elmddm_mlp_forward", "elmddm_mlp_loss_grad", "elmddm_mlp_adam_step",
     "elmddm_mlp_train", "elmddm_mlp_predict",
-    "elmddm_plan_query", "elmddm_graph_capture", "elmddm_graph_launch", "elmddm_graph_info",
+    "elmddm_plan_query", "elmddm_plan_create_ex", "elmddm_plan_is_matrix_free", "elmddm_plan_set_cg",
+    "elmddm_plan_cg_stats", "elmddm_graph_capture", "elmddm_graph_launch", "elmddm_graph_info",
     "elmddm_graph_destroy",
     "elmddm_status_string", "elmddm_last_error",
 ]
@@ -117,6 +120,10 @@ def lib():
         L.elmddm_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]
         L.elmddm_pass_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]
         L.elmddm_plan_query.argtypes = [ctypes.POINTER(Problem), i32, ctypes.POINTER(Sizes)]
+        L.elmddm_plan_create_ex.argtypes = [ctypes.POINTER(Problem), i32, ctypes.c_uint32, ctypes.POINTER(vp)]
+        L.elmddm_plan_is_matrix_free.argtypes = [vp]
+        L.elmddm_plan_set_cg.argtypes = [vp, ctypes.c_double, i32]
+        L.elmddm_plan_cg_stats.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
         L.elmddm_graph_capture.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(SolveArgs), i32, ctypes.POINTER(vp)]
         L.elmddm_graph_launch.argtypes = [vp, vp]
         L.elmddm_graph_info.argtypes = [vp, i32, ctypes.POINTER(Info)]
@@ -179,9 +186,9 @@ def make_problem(x0=0.0, x1=1.0, y0=0.0, y1=1.0, nsub_x=1, nsub_y=1, neurons=1, 
 class Plan:
     """Owns an elmddm_plan (host layout + device workspace)."""
 
-    def __init__(self, problem: Problem, batch: int = 1):
+    def __init__(self, problem: Problem, batch: int = 1, flags: int = 0):
         self._h = ctypes.c_void_p()
-        _check(lib().elmddm_plan_create_batch(ctypes.byref(problem), batch, ctypes.byref(self._h)))
+        _check(lib().elmddm_plan_create_ex(ctypes.byref(problem), batch, flags, ctypes.byref(self._h)))
         s = Sizes()
         _check(lib().elmddm_plan_sizes(self._h, ctypes.byref(s)))
         self.sizes = s
@@ -277,11 +284,26 @@ class Plan:
         return list(ms), n.value
 
     def pass_times(self):
-        """([[gram, cholesky, trsm] ms for passes 1..4] summed over timed solves, number of solves)."""
-        ms = (ctypes.c_double * 12)()
+        """([[gram, cholesky, trsm] ms for passes 1..5] summed over timed solves, number of solves)."""
+        ms = (ctypes.c_double * 15)()
         n = ctypes.c_int32()
         _check(lib().elmddm_pass_times(self._h, ms, ctypes.byref(n)))
-        return [list(ms[3 * p:3 * p + 3]) for p in range(4)], n.value
+        return [list(ms[3 * p:3 * p + 3]) for p in range(5)], n.value
+
+    @property
+    def matrix_free(self):
+        return bool(lib().elmddm_plan_is_matrix_free(self._h))
+
+    def set_cg(self, tol, maxit):
+        _check(lib().elmddm_plan_set_cg(self._h, tol, maxit))
+
+    def cg_stats(self):
+        """(iterations, relative residuals) of the last CG per instance (matrix-free plans)."""
+        b = self.sizes.batch
+        it = (ctypes.c_int32 * b)()
+        rr = (ctypes.c_double * b)()
+        _check(lib().elmddm_plan_cg_stats(self._h, it, rr))
+        return list(it), list(rr)
 
     def set_kernels(self, gram_code, trsm_code):
         _check(lib().elmddm_plan_set_kernels(self._h, gram_code, trsm_code))

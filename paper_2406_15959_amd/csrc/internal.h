@@ -192,4 +192,10 @@ void cg_init(hipStream_t st, int n, const double* b, const double* Sx, double* r
 void cg_step(hipStream_t st, int n, double* x, double* r, double* p, const double* q, double* state, double tol,
              int nrhs);
 
+// Matrix-free interface operator pieces.
+void mf_tpart(hipStream_t st, int NT, int ngeo, int kpad, const double* P, int ldp, long long sP,
+              const int32_t* gidx, const double* v, long long nG, double* t, long long sT, bool shared);
+void mf_mv(hipStream_t st, int nE, int mg, const int32_t* mstart, const int32_t* mE, const double* Mbuf,
+           long long sM, const double* v, long long nG, double* w, long long sW, int ninst);
+
 }  // namespace elmddm

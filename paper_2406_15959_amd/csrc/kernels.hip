@@ -1886,3 +1886,82 @@ void cg_step(hipStream_t st, int n, double* x, double* r, double* p, const doubl
 }
 
 }  // namespace elmddm
+
+// ---------------------------------------------------------------------------
+// Matrix-free interface operator (Section 3, eq. schur, applied without
+// forming S):  S v = sum_s R_s^T (I - T_s) R_s v + M^T M v, with T_s the
+// Y^T Y block of the Schur products P_s and M given by its nonzero blocks
+// M_{g,E} (flux edge g x value edge E).  The sum over owners and the M^T w
+// part are done by schur_rhs_kernel on the outputs of these two kernels.
+// ---------------------------------------------------------------------------
+namespace elmddm {
+
+// t_s = v_s - T_s v_s with v_s = v[gidx_s] (zero for unused slots); one
+// workgroup per subdomain of the batch, v_s staged in LDS, one wave per row
+// block of T_s (lanes along the contiguous column index).
+__global__ __launch_bounds__(256) void mf_tpart_kernel(int kpad, const double* P, int ldp, long long sP,
+                                                       const int32_t* gidx, const double* v, long long nG,
+                                                       double* t, long long sT, int ngeo, bool shared)
+{
+    extern __shared__ double vs[];
+    const int s = blockIdx.x;
+    const int sg = s % ngeo;
+    const long long inst = s / ngeo;
+    v += inst * nG;
+    // one operator per instance, or one shared by all right-hand sides
+    const double* Ps = P + (shared ? sg : s) * sP;
+    for (int i = threadIdx.x; i < kpad; i += blockDim.x) {
+        const int gi = gidx[(long long)sg * kpad + i];
+        vs[i] = gi >= 0 ? v[gi] : 0.0;
+    }
+    __syncthreads();
+    // T is symmetric: (T v)[r] = sum_j T[j][r] v[j], column r of T contiguous
+    const int lane = threadIdx.x & 63;
+    for (int r = threadIdx.x >> 6; r < kpad; r += blockDim.x >> 6) {
+        const double* col = Ps + (long long)r * ldp;
+        double acc = 0.0;
+        for (int j = lane; j < kpad; j += 64) acc += col[j] * vs[j];
+        acc = wave_sum(acc);
+        if (lane == 0) t[s * sT + r] = vs[r] - acc;
+    }
+}
+
+// w_g = -sum_{E in adj(g)} M_{g,E} v_E for every flux edge g (blocks stored
+// column-major mg x mg: element (p, r) at r * mg + p).  One 64-thread group
+// per edge; mstart[g] .. mstart[g+1] are g's blocks, mE their value edges.
+__global__ void mf_mv_kernel(int mg, const int32_t* mstart, const int32_t* mE, const double* Mbuf,
+                             long long sM, const double* v, long long nG, double* w, long long sW)
+{
+    const int g = blockIdx.x;
+    const long long inst = blockIdx.y;
+    Mbuf += inst * sM;
+    v += inst * nG;
+    w += inst * sW;
+    const int mm = mg * mg;
+    for (int p = threadIdx.x; p < mg; p += blockDim.x) {
+        double acc = 0.0;
+        for (int it = mstart[g]; it < mstart[g + 1]; ++it) {
+            const double* Mb = Mbuf + (long long)it * mm;
+            const double* vE = v + (long long)mE[it] * mg;
+            for (int r = 0; r < mg; ++r) acc += Mb[(long long)r * mg + p] * vE[r];
+        }
+        w[(long long)g * mg + p] = -acc;
+    }
+}
+
+void mf_tpart(hipStream_t st, int NT, int ngeo, int kpad, const double* P, int ldp, long long sP,
+              const int32_t* gidx, const double* v, long long nG, double* t, long long sT, bool shared)
+{
+    if (kpad <= 0) return;
+    hipLaunchKernelGGL(mf_tpart_kernel, dim3(NT), dim3(256), kpad * sizeof(double), st, kpad, P, ldp, sP, gidx,
+                       v, nG, t, sT, ngeo, shared);
+}
+
+void mf_mv(hipStream_t st, int nE, int mg, const int32_t* mstart, const int32_t* mE, const double* Mbuf,
+           long long sM, const double* v, long long nG, double* w, long long sW, int ninst)
+{
+    if (nE <= 0) return;
+    hipLaunchKernelGGL(mf_mv_kernel, dim3(nE, ninst), dim3(64), 0, st, mg, mstart, mE, Mbuf, sM, v, nG, w, sW);
+}
+
+}  // namespace elmddm

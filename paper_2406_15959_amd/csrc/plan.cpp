@@ -38,6 +38,17 @@ elmddm_status fail(elmddm_status st, const std::string& msg)
 
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
+// tanh feature blocks grow worse conditioned with the neuron count (at the
+// configured scales: column-scaled kappa ~1e9 at n = 400, 1e12..1e13 at
+// n = 800, ~1e15 at n = 1000); each shifted pass divides kappa by ~1e4 and
+// the unshifted passes need it below ~1e8
+int default_passes(int n) { return n >= 900 ? 5 : (n >= 600 ? 4 : 3); }
+
+long long interface_count(const elmddm_problem& p)
+{
+    return ((long long)(p.nsub_x - 1) * p.nsub_y + (long long)p.nsub_x * (p.nsub_y - 1)) * p.m_ifc_edge;
+}
+
 struct EdgeOwner {
     int s;     // subdomain
     int slot;  // local interface slot of the edge's first point
@@ -69,8 +80,8 @@ struct elmddm_plan {
     // device memory
     std::vector<void*> allocs;
     uint64_t bytes = 0;
-    double *X0 = nullptr, *X1 = nullptr, *G = nullptr, *Linv[4] = {nullptr, nullptr, nullptr, nullptr};
-    // CholeskyQR passes (3 or 4): passes 1 .. npass - 2 are shifted, the last
+    double *X0 = nullptr, *X1 = nullptr, *G = nullptr, *Linv[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    // CholeskyQR passes (3 to 5): passes 1 .. npass - 2 are shifted, the last
     // one also factors the rhs row.  After a solve, Qprev holds Q of pass
     // npass - 1 (all rows) and Xfin the last pass's interface rows, h row and
     // flux rows.
@@ -94,21 +105,32 @@ struct elmddm_plan {
     bool schur_valid = false;
     hipStream_t last_stream = nullptr;
     bool solved = false;
+    // interface system without a dense S: CG on the matrix-free operator
+    bool mfree = false;
+    double cg_tol = 1e-12;
+    int cg_maxit = 100000;
+    std::vector<int32_t> cg_iters;
+    std::vector<double> cg_relres;
+    bool cg_failed = false;
+    double *tbuf = nullptr, *wbuf = nullptr, *mfX = nullptr, *mfR = nullptr, *mfP = nullptr, *mfQ = nullptr,
+           *mfS = nullptr;
+    int32_t *d_mstart = nullptr, *d_mE = nullptr, *d_ident = nullptr;
     bool factors_valid = false;   // the workspace holds the factors of the last solve
     // further right-hand sides (elmddm_plan_reserve_rhs / elmddm_solve_rhs)
     int rhs_cap = 0;
     double *Fr = nullptr, *Tm = nullptr, *Hm = nullptr, *Ph = nullptr, *abufR = nullptr;
     double *yR = nullptr, *uR = nullptr, *Vm = nullptr;
     double *cgX = nullptr, *cgR = nullptr, *cgP = nullptr, *cgQ = nullptr, *cgS = nullptr;
+    double *tbufR = nullptr, *wbufR = nullptr;   // matrix-free operator scratch for R right-hand sides
     int32_t *d_rb = nullptr, *d_re = nullptr;   // row band of each 64-column block of S
     // stage timing
     bool timing = false;
     hipEvent_t ev[ELMDDM_NUM_STAGES + 1] = {};
-    hipEvent_t pev[13] = {};  // per-pass Gram / Cholesky / triangular-solve boundaries
+    hipEvent_t pev[16] = {};  // per-pass Gram / Cholesky / triangular-solve boundaries
     bool ev_ready = false;
     bool ev_pending = false;
     double stage_ms[ELMDDM_NUM_STAGES] = {};
-    double pass_ms[12] = {};  // per CholeskyQR pass: Gram, Cholesky + inverses, triangular solve
+    double pass_ms[15] = {};  // per CholeskyQR pass: Gram, Cholesky + inverses, triangular solve
     int timed_solves = 0;
 
     bool dry = false;   // size query only: count bytes, allocate nothing
@@ -416,9 +438,17 @@ elmddm_status build(elmddm_plan* P)
         qdesc.insert(qdesc.end(), a, a + 4);
     }
     P->n_mblocks = (int)(mdesc.size() / 8);
-    const size_t nEE = (size_t)P->nE * P->nE;
+    // matrix-free operator: the value edge of every M block, blocks grouped by flux edge
+    std::vector<int32_t> mstart(P->nE + 1, 0), mE;
+    for (int g = 0; g < P->nE; ++g) {
+        mstart[g + 1] = mstart[g] + (int32_t)adj[g].size();
+        for (int E : adj[g]) mE.push_back(E);
+    }
+    std::vector<int32_t> ident(std::max(P->nE, 1));
+    for (int e = 0; e < P->nE; ++e) ident[e] = e;
+    const size_t nEE = P->mfree ? 0 : (size_t)P->nE * P->nE;
     std::vector<std::vector<int32_t>> tl(nEE), ml(nEE);
-    for (int s = 0; s < N; ++s)
+    for (int s = 0; s < N && !P->mfree; ++s)
         for (auto& e1 : sub_edges[s])
             for (auto& e2 : sub_edges[s]) {
                 const size_t blk = (size_t)e1.first + (size_t)e2.first * P->nE;
@@ -430,6 +460,7 @@ elmddm_status build(elmddm_plan* P)
             gl[E1].push_back(mid[{g, E1}]);
             gl[E1].push_back(g);
             for (int E2 : adj[g]) {
+                if (P->mfree) break;
                 const size_t blk = (size_t)E1 + (size_t)E2 * P->nE;
                 ml[blk].push_back(mid[{g, E1}]);
                 ml[blk].push_back(mid[{g, E2}]);
@@ -469,7 +500,7 @@ elmddm_status build(elmddm_plan* P)
         for (int r = 0; r < P->nE; ++r) perm[key[r].second] = r;
         std::vector<int> lastb(P->nE, 0);
         for (int e2 = 0; e2 < P->nE; ++e2) lastb[perm[e2]] = perm[e2];
-        for (int e1 = 0; e1 < P->nE; ++e1)
+        for (int e1 = 0; e1 < P->nE && !P->mfree; ++e1)
             for (int e2 = 0; e2 < P->nE; ++e2) {
                 const size_t blk = (size_t)e1 + (size_t)e2 * P->nE;
                 if (tl[blk].empty() && ml[blk].empty()) continue;
@@ -531,12 +562,22 @@ elmddm_status build(elmddm_plan* P)
     TRY(P->dalloc(&P->P, NT * P->sP));
     TRY(P->dalloc(&P->Mbuf, Bn * std::max(P->n_mblocks, 1) * mg * mg));
     TRY(P->dalloc(&P->abuf, Bn * std::max(P->nE, 1) * mg));
-    TRY(P->dalloc(&P->Sx, Bn * P->lds * nGm));
-    TRY(P->dalloc(&P->DinvS, Bn * std::max(P->nblkS, 1) * NB * NB));
+    if (!P->mfree) {
+        TRY(P->dalloc(&P->Sx, Bn * P->lds * nGm));
+        TRY(P->dalloc(&P->DinvS, Bn * std::max(P->nblkS, 1) * NB * NB));
+        TRY(P->dalloc(&P->SL, Bn * P->lds * nGm));
+    } else {
+        TRY(P->upload(&P->d_mstart, mstart));
+        TRY(P->upload(&P->d_mE, mE));
+        TRY(P->upload(&P->d_ident, ident));
+        TRY(P->dalloc(&P->tbuf, NT * std::max(P->kpad, 1)));
+        TRY(P->dalloc(&P->wbuf, Bn * std::max(P->nE, 1) * mg));
+        for (double** q : {&P->mfX, &P->mfR, &P->mfP, &P->mfQ}) TRY(P->dalloc(q, Bn * nGm));
+        TRY(P->dalloc(&P->mfS, 4 * Bn));
+    }
     TRY(P->dalloc(&P->yvec, Bn * nGm));
     TRY(P->dalloc(&P->dsave, std::max(NT * n, Bn * nGm)));
     TRY(P->dalloc(&P->uperm, Bn * nGm));
-    TRY(P->dalloc(&P->SL, Bn * P->lds * nGm));
     TRY(P->dalloc(&P->bs1, NT * n));
     TRY(P->dalloc(&P->bs2, NT * n));
     TRY(P->dalloc(&P->d_info, 1));
@@ -547,7 +588,7 @@ elmddm_status build(elmddm_plan* P)
         if (hipMemset(P->Linv[i], 0, NT * P->sL * sizeof(double)) != hipSuccess)
             return fail(ELMDDM_HIP_ERROR, "hipMemset failed during plan creation");
     // Entries of the interface factor outside the envelope are never written and read as zero.
-    if (hipMemset(P->SL, 0, Bn * P->lds * nGm * sizeof(double)) != hipSuccess)
+    if (P->SL && hipMemset(P->SL, 0, Bn * P->lds * nGm * sizeof(double)) != hipSuccess)
         return fail(ELMDDM_HIP_ERROR, "hipMemset failed during plan creation");
     if (hipMemset(P->X1, 0, NT * P->sX * sizeof(double)) != hipSuccess)
         return fail(ELMDDM_HIP_ERROR, "hipMemset failed during plan creation");
@@ -594,8 +635,8 @@ elmddm_status elmddm_plan_create(const elmddm_problem* problem, elmddm_plan** pl
     return elmddm_plan_create_batch(problem, 1, plan);
 }
 
-elmddm_status elmddm_plan_create_batch(const elmddm_problem* problem, int32_t batch,
-                                       elmddm_plan** plan)
+elmddm_status elmddm_plan_create_ex(const elmddm_problem* problem, int32_t batch, uint32_t flags,
+                                    elmddm_plan** plan)
 {
     if (!plan) return fail(ELMDDM_INVALID_ARG, "plan output pointer is NULL");
     *plan = nullptr;
@@ -603,6 +644,8 @@ elmddm_status elmddm_plan_create_batch(const elmddm_problem* problem, int32_t ba
     if (st != ELMDDM_OK) return st;
     if (batch < 1 || (int64_t)batch * problem->nsub_x * problem->nsub_y > (1 << 20))
         return fail(ELMDDM_INVALID_ARG, "batch must be >= 1 and batch * nsub <= 2^20");
+    if ((flags & ELMDDM_PLAN_MATRIX_FREE) && (flags & ELMDDM_PLAN_DENSE))
+        return fail(ELMDDM_INVALID_ARG, "MATRIX_FREE and DENSE are exclusive");
     elmddm_plan* P = new (std::nothrow) elmddm_plan();
     if (!P) return fail(ELMDDM_OOM, "host allocation failed");
     P->p = *problem;
@@ -610,10 +653,12 @@ elmddm_status elmddm_plan_create_batch(const elmddm_problem* problem, int32_t ba
     // one fused launch per envelope step is latency-optimal for few systems;
     // a separate panel + trailing GEMM wins once several systems share the launches
     P->env_fused = batch < 4;
-    // tanh feature blocks grow worse conditioned with the neuron count (at the
-    // configured scales: column-scaled kappa ~1e9 at n = 400, 1e12..1e13 at
-    // n = 800); one shifted pass covers kappa up to about 1e12, two beyond
-    P->npass = problem->neurons >= 600 ? 4 : 3;
+    P->npass = default_passes(problem->neurons);
+    // dense interface factorisation unless its three nG x nG arrays would
+    // exceed 64 GB (or the caller chooses)
+    const double nGd = (double)interface_count(*problem);
+    P->mfree = (flags & ELMDDM_PLAN_MATRIX_FREE) ||
+               (!(flags & ELMDDM_PLAN_DENSE) && 3.0 * batch * nGd * nGd * 8.0 > 64e9);
     try {
         st = build(P);
     } catch (const std::bad_alloc&) {
@@ -627,6 +672,11 @@ elmddm_status elmddm_plan_create_batch(const elmddm_problem* problem, int32_t ba
     return ELMDDM_OK;
 }
 
+elmddm_status elmddm_plan_create_batch(const elmddm_problem* problem, int32_t batch, elmddm_plan** plan)
+{
+    return elmddm_plan_create_ex(problem, batch, 0, plan);
+}
+
 elmddm_status elmddm_plan_query(const elmddm_problem* problem, int32_t batch, elmddm_sizes* sizes)
 {
     if (!sizes) return fail(ELMDDM_INVALID_ARG, "sizes is NULL");
@@ -637,7 +687,9 @@ elmddm_status elmddm_plan_query(const elmddm_problem* problem, int32_t batch, el
     elmddm_plan Q;
     Q.p = *problem;
     Q.B = batch;
-    Q.npass = problem->neurons >= 600 ? 4 : 3;
+    Q.npass = default_passes(problem->neurons);
+    const double nGd = (double)interface_count(*problem);
+    Q.mfree = 3.0 * batch * nGd * nGd * 8.0 > 64e9;
     Q.dry = true;
     try {
         st = build(&Q);
@@ -701,6 +753,7 @@ elmddm_status elmddm_assemble(elmddm_plan* P, const double* W, const double* b, 
 elmddm_status elmddm_plan_keep_schur(elmddm_plan* P, int32_t keep)
 {
     if (!P) return fail(ELMDDM_INVALID_ARG, "NULL plan");
+    if (keep && P->mfree) return fail(ELMDDM_UNSUPPORTED, "a matrix-free plan never forms S");
     if (keep && !P->Skeep) {
         elmddm_status st = P->dalloc(&P->Skeep, (size_t)P->lds * std::max(P->nG, 1));
         if (st != ELMDDM_OK) return st;
@@ -709,10 +762,32 @@ elmddm_status elmddm_plan_keep_schur(elmddm_plan* P, int32_t keep)
     return ELMDDM_OK;
 }
 
+elmddm_status elmddm_plan_set_cg(elmddm_plan* P, double tol, int32_t maxit)
+{
+    if (!P) return fail(ELMDDM_INVALID_ARG, "NULL plan");
+    if (!(tol > 0.0 && tol < 1.0) || maxit < 1) return fail(ELMDDM_INVALID_ARG, "need 0 < tol < 1 and maxit >= 1");
+    P->cg_tol = tol;
+    P->cg_maxit = maxit;
+    return ELMDDM_OK;
+}
+
+elmddm_status elmddm_plan_cg_stats(const elmddm_plan* P, int32_t* iters, double* relres)
+{
+    if (!P || !iters || !relres) return fail(ELMDDM_INVALID_ARG, "NULL argument");
+    if (!P->mfree) return fail(ELMDDM_UNSUPPORTED, "the plan factors the interface system directly");
+    for (int q = 0; q < P->B; ++q) {
+        iters[q] = q < (int)P->cg_iters.size() ? P->cg_iters[q] : 0;
+        relres[q] = q < (int)P->cg_relres.size() ? P->cg_relres[q] : 0.0;
+    }
+    return ELMDDM_OK;
+}
+
+int32_t elmddm_plan_is_matrix_free(const elmddm_plan* P) { return P && P->mfree ? 1 : 0; }
+
 elmddm_status elmddm_plan_set_passes(elmddm_plan* P, int32_t npass)
 {
     if (!P) return fail(ELMDDM_INVALID_ARG, "NULL plan");
-    if (npass != 3 && npass != 4) return fail(ELMDDM_INVALID_ARG, "npass must be 3 or 4");
+    if (npass < 3 || npass > 5) return fail(ELMDDM_INVALID_ARG, "npass must be 3, 4 or 5");
     for (int i = 0; i < npass; ++i)
         if (!P->Linv[i]) {
             const size_t cnt = (size_t)P->NT * P->sL;
@@ -746,6 +821,69 @@ elmddm_status elmddm_get_schur(elmddm_plan* P, double* S, double* rhs, void* str
     unpermute(st, P->nE, P->mg, P->d_perm, P->uperm, rhs, 1);
     return check_launch("get_schur");
 }
+
+namespace {
+
+struct CgBufs {
+    double *r, *p, *q, *state, *t, *w;
+};
+
+// y = S x for R systems with the matrix-free operator (Section 3, eq. schur
+// applied without forming S).  shared: one operator (instance 0) for all R.
+void apply_mfree(elmddm_plan* P, hipStream_t st, const double* x, double* y, int R, bool shared, const CgBufs& cb)
+{
+    const int N = P->N;
+    const long long sM = shared ? 0 : (long long)P->n_mblocks * P->mg * P->mg;
+    mf_tpart(st, N * R, N, P->kpad, P->P, P->ldp, P->sP, P->d_gidx, x, P->nG, cb.t, P->kpad, shared);
+    mf_mv(st, P->nE, P->mg, P->d_mstart, P->d_mE, P->Mbuf, sM, x, P->nG, cb.w, (long long)P->nE * P->mg, R);
+    schur_rhs(st, P->nE, P->mg, P->d_qdesc, P->d_gptr, P->d_gdesc, cb.t, 1, P->kpad, 0, P->Mbuf, cb.w, y, 1,
+              P->d_ident, N, sM, (long long)P->nE * P->mg, P->nG, R);
+}
+
+// CG (stop at ||b - S x|| <= tol ||b||) for R systems on the matrix-free
+// operator; x holds the start.  Polls the convergence flags every 32 steps.
+elmddm_status run_cg(elmddm_plan* P, hipStream_t st, const double* b, double* x, int R, double tol, int maxit,
+                     bool shared, const CgBufs& cb)
+{
+    const int nG = P->nG;
+    apply_mfree(P, st, x, cb.q, R, shared, cb);
+    cg_init(st, nG, b, cb.q, cb.r, cb.p, cb.state, tol, R);
+    std::vector<double> state(4 * R, 0.0);
+    auto poll = [&]() -> elmddm_status {
+        if (hipMemcpyAsync(state.data(), cb.state, 4 * R * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return check_launch("CG poll");
+        return ELMDDM_OK;
+    };
+    elmddm_status est = poll();
+    if (est != ELMDDM_OK) return est;
+    auto all_done = [&]() {
+        for (int q = 0; q < R; ++q)
+            if (state[4 * q + 2] == 0.0) return false;
+        return true;
+    };
+    for (int it = 0; it < maxit && !all_done(); ++it) {
+        apply_mfree(P, st, cb.p, cb.q, R, shared, cb);
+        cg_step(st, nG, x, cb.r, cb.p, cb.q, cb.state, tol, R);
+        if ((it & 31) == 31 || it + 1 == maxit) {
+            est = poll();
+            if (est != ELMDDM_OK) return est;
+        }
+    }
+    est = poll();
+    if (est != ELMDDM_OK) return est;
+    P->cg_iters.assign(R, 0);
+    P->cg_relres.assign(R, 0.0);
+    P->cg_failed = false;
+    for (int q = 0; q < R; ++q) {
+        P->cg_iters[q] = (int32_t)state[4 * q + 3];
+        P->cg_relres[q] = state[4 * q + 1] > 0.0 ? std::sqrt(state[4 * q] / state[4 * q + 1]) : 0.0;
+        if (state[4 * q + 2] != 1.0) P->cg_failed = true;
+    }
+    return check_launch("CG");
+}
+
+}  // namespace
 
 elmddm_status elmddm_solve(elmddm_plan* P, const double* W, const double* b, const double* f,
                            const double* g, const double* coef, double* u_gamma, double* c,
@@ -834,34 +972,53 @@ elmddm_status elmddm_solve(elmddm_plan* P, const double* W, const double* b, con
         const long long sM = (long long)P->n_mblocks * P->mg * P->mg;
         schur_mblocks(st, P->n_mblocks, P->d_mdesc, P->P, P->ldp, P->sP, cbase, P->mg, P->Mbuf, P->N, B);
         schur_avec(st, P->nE, P->d_adesc, P->P, P->ldp, P->sP, cbase, P->kpad, P->mg, P->abuf, P->N, B);
-        schur_sblocks(st, P->nE, P->mg, P->d_tptr, P->d_tdesc, P->d_mptr, P->d_mlist, P->P, P->ldp,
-                      P->sP, P->Mbuf, P->Sx, P->lds, P->d_perm, P->N, sM, sS, B);
-        schur_rhs(st, P->nE, P->mg, P->d_qdesc, P->d_gptr, P->d_gdesc, P->P, P->ldp, P->sP, P->kpad,
-                  P->Mbuf, P->abuf, P->yvec, 1, P->d_perm, P->N, sM, (long long)P->nE * P->mg,
-                  P->nG, B);
-        P->mark(5, st);
-        if (P->keep_schur && P->Skeep) {
-            (void)hipMemcpyAsync(P->Skeep, P->Sx, (size_t)P->lds * P->nG * sizeof(double),
-                                 hipMemcpyDeviceToDevice, st);
-            copy_row(st, P->yvec, 1, 0, P->Skeep + P->nG, P->lds, 0, P->nG, 1);
-            P->schur_valid = true;
+        if (P->mfree) {
+            // the paper's interface solver: CG on the matrix-free operator, in
+            // the interface numbering (identity edge order), zero start
+            schur_rhs(st, P->nE, P->mg, P->d_qdesc, P->d_gptr, P->d_gdesc, P->P, P->ldp, P->sP, P->kpad,
+                      P->Mbuf, P->abuf, P->yvec, 1, P->d_ident, P->N, sM, (long long)P->nE * P->mg, P->nG, B);
+            P->mark(5, st);
+            P->mark(6, st);
+            est = check_launch("Schur pieces");
+            if (est != ELMDDM_OK) return est;
+            if (hipMemsetAsync(P->mfX, 0, (size_t)B * P->nG * sizeof(double), st) != hipSuccess)
+                return check_launch("CG start");
+            est = run_cg(P, st, P->yvec, P->mfX, B, P->cg_tol, P->cg_maxit, false,
+                         CgBufs{P->mfR, P->mfP, P->mfQ, P->mfS, P->tbuf, P->wbuf});
+            if (est != ELMDDM_OK) return est;
+            if (hipMemcpyAsync(u_gamma, P->mfX, (size_t)B * P->nG * sizeof(double), hipMemcpyDeviceToDevice, st) !=
+                hipSuccess)
+                return check_launch("CG result copy");
+        } else {
+            schur_sblocks(st, P->nE, P->mg, P->d_tptr, P->d_tdesc, P->d_mptr, P->d_mlist, P->P, P->ldp,
+                          P->sP, P->Mbuf, P->Sx, P->lds, P->d_perm, P->N, sM, sS, B);
+            schur_rhs(st, P->nE, P->mg, P->d_qdesc, P->d_gptr, P->d_gdesc, P->P, P->ldp, P->sP, P->kpad,
+                      P->Mbuf, P->abuf, P->yvec, 1, P->d_perm, P->N, sM, (long long)P->nE * P->mg,
+                      P->nG, B);
+            P->mark(5, st);
+            if (P->keep_schur && P->Skeep) {
+                (void)hipMemcpyAsync(P->Skeep, P->Sx, (size_t)P->lds * P->nG * sizeof(double),
+                                     hipMemcpyDeviceToDevice, st);
+                copy_row(st, P->yvec, 1, 0, P->Skeep + P->nG, P->lds, 0, P->nG, 1);
+                P->schur_valid = true;
+            }
+            // Interface solve in the permuted order: envelope Cholesky with the
+            // forward substitution fused (yvec <- L^{-1} rhs), then L^T u = y
+            // block by block, then back to the interface numbering.
+            const long long sDS = (long long)P->nblkS * NB * NB;
+            envelope_potrf(st, P->Sx, P->lds, sS, P->SL, P->lds, sS, P->nG, P->rend.data(), P->DinvS, sDS,
+                           P->d_info, 4, P->dsave, P->yvec, P->nG, B, P->env_fused);
+            P->mark(6, st);
+            const int BR = 4 * NB;
+            for (int j0 = (P->nG - 1) / BR * BR; j0 >= 0; j0 -= BR) {
+                const int br = std::min(BR, P->nG - j0);
+                trsv_lower_t_block(st, P->SL, P->lds, sS, j0, br, P->kbeg[j0 / NB], P->DinvS, sDS,
+                                   P->yvec, P->uperm, P->nG, B);
+            }
+            unpermute(st, P->nE, P->mg, P->d_perm, P->uperm, u_gamma, B);
+            est = check_launch("interface solve");
+            if (est != ELMDDM_OK) return est;
         }
-        // Interface solve in the permuted order: envelope Cholesky with the
-        // forward substitution fused (yvec <- L^{-1} rhs), then L^T u = y
-        // block by block, then back to the interface numbering.
-        const long long sDS = (long long)P->nblkS * NB * NB;
-        envelope_potrf(st, P->Sx, P->lds, sS, P->SL, P->lds, sS, P->nG, P->rend.data(), P->DinvS, sDS,
-                       P->d_info, 4, P->dsave, P->yvec, P->nG, B, P->env_fused);
-        P->mark(6, st);
-        const int BR = 4 * NB;
-        for (int j0 = (P->nG - 1) / BR * BR; j0 >= 0; j0 -= BR) {
-            const int br = std::min(BR, P->nG - j0);
-            trsv_lower_t_block(st, P->SL, P->lds, sS, j0, br, P->kbeg[j0 / NB], P->DinvS, sDS,
-                               P->yvec, P->uperm, P->nG, B);
-        }
-        unpermute(st, P->nE, P->mg, P->d_perm, P->uperm, u_gamma, B);
-        est = check_launch("interface solve");
-        if (est != ELMDDM_OK) return est;
     } else {
         P->mark(5, st);
         P->mark(6, st);
@@ -886,7 +1043,7 @@ elmddm_status elmddm_plan_reserve_rhs(elmddm_plan* P, int32_t max_rhs)
     if (max_rhs < 1 || max_rhs > 4096) return fail(ELMDDM_INVALID_ARG, "max_rhs must be in [1, 4096]");
     if (max_rhs <= P->rhs_cap) return ELMDDM_OK;
     for (double** q : {&P->Fr, &P->Tm, &P->Hm, &P->Ph, &P->abufR, &P->yR, &P->uR, &P->Vm, &P->cgX, &P->cgR,
-                       &P->cgP, &P->cgQ, &P->cgS}) {
+                       &P->cgP, &P->cgQ, &P->cgS, &P->tbufR, &P->wbufR}) {
         if (*q) {
             P->allocs.erase(std::find(P->allocs.begin(), P->allocs.end(), (void*)*q));
             (void)hipFree(*q);
@@ -907,7 +1064,11 @@ elmddm_status elmddm_plan_reserve_rhs(elmddm_plan* P, int32_t max_rhs)
     for (double** q : {&P->cgX, &P->cgR, &P->cgP, &P->cgQ})
         if ((st = P->dalloc(q, R * nGm)) != ELMDDM_OK) return st;
     if ((st = P->dalloc(&P->cgS, 4 * R)) != ELMDDM_OK) return st;
-    if (!P->d_rb && P->nblkS > 0) {
+    if (P->mfree) {
+        if ((st = P->dalloc(&P->tbufR, N * R * std::max(P->kpad, 1))) != ELMDDM_OK) return st;
+        if ((st = P->dalloc(&P->wbufR, R * std::max(P->nE, 1) * P->mg)) != ELMDDM_OK) return st;
+    }
+    if (!P->mfree && !P->d_rb && P->nblkS > 0) {
         if ((st = P->upload(&P->d_rb, P->kbeg)) != ELMDDM_OK) return st;
         if ((st = P->upload(&P->d_re, P->rend)) != ELMDDM_OK) return st;
     }
@@ -948,7 +1109,7 @@ void rhs_stage(elmddm_plan* P, hipStream_t st, int R, const double* f, const dou
              (long long)R * n, 0.0, P->Ph, N * ldp, ldp, N);
     schur_avec(st, P->nE, P->d_adesc, P->Ph, ldp, ldp, kp + 16, 0, mg, P->abufR, N, R);
     schur_rhs(st, P->nE, mg, P->d_qdesc, P->d_gptr, P->d_gdesc, P->Ph, ldp, ldp, 0, P->Mbuf, P->abufR, P->yR, 1,
-              P->d_perm, N, 0, (long long)P->nE * mg, nG, R);
+              P->mfree ? P->d_ident : P->d_perm, N, 0, (long long)P->nE * mg, nG, R);
 }
 
 }  // namespace
@@ -965,7 +1126,16 @@ elmddm_status elmddm_solve_rhs(elmddm_plan* P, int32_t nrhs, const double* f, co
     for (int r0 = 0; r0 < nrhs; r0 += P->rhs_cap) {
         const int R = std::min(P->rhs_cap, nrhs - r0);
         rhs_stage(P, st, R, f + r0 * nf, g ? g + r0 * P->nB : nullptr);
-        if (nG > 0) {
+        if (nG > 0 && P->mfree) {
+            // CG from zero on the shared matrix-free operator
+            double* ur = u_gamma + (long long)r0 * nG;
+            if (hipMemsetAsync(ur, 0, (size_t)R * nG * sizeof(double), st) != hipSuccess)
+                return check_launch("CG start");
+            est = run_cg(P, st, P->yR, ur, R, P->cg_tol, P->cg_maxit, true,
+                         CgBufs{P->cgR, P->cgP, P->cgQ, P->cgS, P->tbufR, P->wbufR});
+            if (est != ELMDDM_OK) return est;
+            if (P->cg_failed) return fail(ELMDDM_NOT_CONVERGED, "interface CG did not reach the tolerance");
+        } else if (nG > 0) {
             // L y = g, then L^T u = y, with the envelope factor of S
             const int BR = 4 * NB;
             for (int j0 = 0; j0 < nG; j0 += BR) {
@@ -1008,7 +1178,7 @@ elmddm_status elmddm_schur_rhs(elmddm_plan* P, int32_t nrhs, const double* f, co
     for (int r0 = 0; r0 < nrhs && P->nG > 0; r0 += P->rhs_cap) {
         const int R = std::min(P->rhs_cap, nrhs - r0);
         rhs_stage(P, st, R, f + r0 * nf, g ? g + r0 * P->nB : nullptr);
-        unpermute(st, P->nE, P->mg, P->d_perm, P->yR, rhs + (long long)r0 * P->nG, R);
+        unpermute(st, P->nE, P->mg, P->mfree ? P->d_ident : P->d_perm, P->yR, rhs + (long long)r0 * P->nG, R);
     }
     return check_launch("schur_rhs");
 }
@@ -1020,10 +1190,35 @@ elmddm_status elmddm_interface_cg(elmddm_plan* P, int32_t nrhs, const double* rh
     if (nrhs < 0 || (P->nG > 0 && (!rhs || !u))) return fail(ELMDDM_INVALID_ARG, "bad nrhs or NULL vector");
     if (!(tol > 0.0) || maxit < 0) return fail(ELMDDM_INVALID_ARG, "tol must be > 0 and maxit >= 0");
     if (P->B != 1) return fail(ELMDDM_UNSUPPORTED, "interface CG needs a plan with batch 1");
-    if (!P->schur_valid) return fail(ELMDDM_INVALID_ARG, "no kept Schur matrix (elmddm_plan_keep_schur before the solve)");
     if (P->rhs_cap < 1) return fail(ELMDDM_INVALID_ARG, "call elmddm_plan_reserve_rhs first");
     hipStream_t st = (hipStream_t)stream;
     const int nG = P->nG, mg = P->mg;
+    if (P->mfree) {
+        if (!P->factors_valid) return fail(ELMDDM_INVALID_ARG, "no factors: call elmddm_solve on this plan first");
+        bool ok = true;
+        for (int r0 = 0; r0 < nrhs && nG > 0; r0 += P->rhs_cap) {
+            const int R = std::min(P->rhs_cap, nrhs - r0);
+            const size_t bytes = (size_t)R * nG * sizeof(double);
+            if (hipMemcpyAsync(P->yR, rhs + (long long)r0 * nG, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+                hipMemcpyAsync(P->cgX, u + (long long)r0 * nG, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess)
+                return check_launch("interface_cg copy");
+            elmddm_status est = run_cg(P, st, P->yR, P->cgX, R, tol, maxit, true,
+                                       CgBufs{P->cgR, P->cgP, P->cgQ, P->cgS, P->tbufR, P->wbufR});
+            if (est != ELMDDM_OK) return est;
+            for (int q = 0; q < R; ++q) {
+                if (iters) iters[r0 + q] = P->cg_iters[q];
+                if (relres) relres[r0 + q] = P->cg_relres[q];
+            }
+            ok = ok && !P->cg_failed;
+            if (hipMemcpyAsync(u + (long long)r0 * nG, P->cgX, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess)
+                return check_launch("interface_cg copy");
+        }
+        elmddm_status est = check_launch("interface_cg");
+        if (est != ELMDDM_OK) return est;
+        if (!ok) return fail(ELMDDM_NOT_CONVERGED, "interface CG did not reach the tolerance");
+        return ELMDDM_OK;
+    }
+    if (!P->schur_valid) return fail(ELMDDM_INVALID_ARG, "no kept Schur matrix (elmddm_plan_keep_schur before the solve)");
     bool all_done = true;
     std::vector<double> state;
     for (int r0 = 0; r0 < nrhs && nG > 0; r0 += P->rhs_cap) {
@@ -1123,6 +1318,7 @@ elmddm_status elmddm_solve_info(elmddm_plan* P, elmddm_info* info)
     if (hipMemcpy(&h, P->d_info, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess)
         return check_launch("solve_info copy");
     info->status = h.status;
+    if (h.status == ELMDDM_OK && P->mfree && P->cg_failed) info->status = ELMDDM_NOT_CONVERGED;
     info->bad_subdomain = h.bad_subdomain == INT_MAX ? -1 : h.bad_subdomain % P->N;
     info->bad_pass = h.bad_pass;
     info->bad_instance = h.bad_subdomain == INT_MAX ? -1 : h.bad_subdomain / P->N;
@@ -1193,7 +1389,7 @@ elmddm_status elmddm_pass_times(elmddm_plan* P, double* ms, int32_t* solves)
 {
     if (!P || !ms) return fail(ELMDDM_INVALID_ARG, "NULL argument");
     P->harvest();
-    for (int i = 0; i < 12; ++i) ms[i] = i < 3 * P->npass ? P->pass_ms[i] : 0.0;
+    for (int i = 0; i < 15; ++i) ms[i] = i < 3 * P->npass ? P->pass_ms[i] : 0.0;
     if (solves) *solves = P->timed_solves;
     return ELMDDM_OK;
 }
@@ -1245,6 +1441,8 @@ elmddm_status elmddm_graph_capture(elmddm_plan* const* plans, const elmddm_solve
     for (int i = 0; i < nsolves; ++i) {
         if (!plans[i]) return fail(ELMDDM_INVALID_ARG, "NULL plan");
         if (plans[i]->timing) return fail(ELMDDM_INVALID_ARG, "stage timing must be off while capturing");
+        if (plans[i]->mfree)
+            return fail(ELMDDM_UNSUPPORTED, "matrix-free plans poll their CG from the host and cannot be captured");
     }
     elmddm_graph* G = new (std::nothrow) elmddm_graph();
     if (!G) return fail(ELMDDM_OOM, "host allocation failed");

@@ -90,3 +90,15 @@ def test_ragged_problem_draws_are_reproducible_and_cover_the_shapes():
     assert {P.nsub_x for P in a} == {4, 8, 16} and {P.neurons for P in a} == {100, 200, 400, 800}
     for P in a:
         assert P.q_x ** 2 >= P.neurons and P.op == wl.OP_VARCOEF and 1 <= P.k1 <= 3
+
+
+def test_the_32x32_case_sizes_to_a_matrix_free_plan():
+    """126976 interface unknowns: a dense S would need 3 x 129 GB; the size query
+    (matrix-free by default there) stays within one GPU."""
+    import workload as wl
+    from paper_2406_15959_amd import binding as B
+    P = wl.CONFIG_32x32
+    s = B.plan_query(B.make_problem(P.x0, P.x1, P.y0, P.y1, P.nsub_x, P.nsub_y, P.neurons, P.q_x, P.q_y,
+                                    P.m_bdry_edge, P.m_ifc_edge, P.op), 1)
+    assert s.n_interface == 126976
+    assert s.device_bytes < 200e9

@@ -1,0 +1,126 @@
+"""Matrix-free interface solve (the paper's CG on S applied from the
+per-subdomain blocks, S never formed) against the oracle and the dense path."""
+import numpy as np
+import pytest
+
+import workload as wl
+from gpu_helpers import gpu_solve, oracle_solve, to_c_problem
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP64 = 1e-8
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def mfree_plan(P, batch=1, tol=1e-13):
+    from paper_2406_15959_amd import binding as B
+    plan = B.Plan(to_c_problem(P), batch=batch, flags=B.PLAN_MATRIX_FREE)
+    assert plan.matrix_free
+    plan.set_cg(tol, 200000)
+    return plan
+
+
+CASES = [
+    ("small-2x2", wl.CONFIG_SMALL, 1000),
+    ("ragged-3x2-varcoef", wl.Problem(3, 2, 70, 11, 9, 10, 13, op=wl.OP_VARCOEF, R=2.0, k1=1, k2=3), 7),
+    ("4x3-n130", wl.Problem(4, 3, 130, 13, 12, 12, 17, R=2.5), 9),
+]
+
+
+@pytest.mark.parametrize("name,P,seed", CASES, ids=[c[0] for c in CASES])
+def test_matrix_free_solve_matches_oracle(gpu, name, P, seed):
+    plan = mfree_plan(P)
+    g = gpu_solve(P, seed, plan=plan)
+    o = oracle_solve(P, seed)
+    assert g["info"].status == 0
+    its, res = plan.cg_stats()
+    assert 0 < its[0] < 200000 and res[0] <= 1e-13
+    assert rel(g["u_gamma"], o["u_gamma"]) <= TOL_FP64
+    assert rel(g["uh"], o["uh"]) <= TOL_FP64
+
+
+def test_matrix_free_equals_dense_on_8x8(gpu):
+    P = wl.CONFIG_8x8
+    gm = gpu_solve(P, 2003, plan=mfree_plan(P))
+    gd = gpu_solve(P, 2003)
+    assert gm["info"].status == 0 and gd["info"].status == 0
+    assert rel(gm["u_gamma"], gd["u_gamma"]) <= 1e-9
+    assert rel(gm["uh"], gd["uh"]) <= 1e-9
+
+
+def test_matrix_free_batch_and_not_converged(gpu):
+    """Two instances with their own operators; a too small iteration cap reports NOT_CONVERGED."""
+    import torch
+    from paper_2406_15959_amd import binding as B
+    P = wl.Problem(3, 3, 60, 10, 10, 8, 6, R=2.0)
+    plan = mfree_plan(P, batch=2)
+    s = plan.sizes
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+    f, g, _ = wl.sample_data(P, plan.points(B.POINTS_INTERIOR), plan.points(B.POINTS_BOUNDARY))
+    (W0, b0), (W1, b1) = wl.hidden_params(P, 31), wl.hidden_params(P, 32)
+    du = torch.zeros(2 * s.n_interface, dtype=torch.float64, device=dev)
+    dc = torch.zeros(2 * s.nsub * s.neurons, dtype=torch.float64, device=dev)
+    plan.solve(t(np.stack([W0, W1])), t(np.stack([b0, b1])), t(np.stack([f, f])), t(np.stack([g, g])), None, du, dc)
+    assert plan.solve_info().status == 0
+    for k, seed in enumerate((31, 32)):
+        o = oracle_solve(P, seed)
+        assert rel(du[k * s.n_interface:(k + 1) * s.n_interface].cpu().numpy(), o["u_gamma"]) <= TOL_FP64
+    plan.set_cg(1e-13, 3)
+    plan.solve(t(np.stack([W0, W1])), t(np.stack([b0, b1])), t(np.stack([f, f])), t(np.stack([g, g])), None, du, dc)
+    assert plan.solve_info().status == B.NOT_CONVERGED
+    assert plan.cg_stats()[0] == [3, 3]
+
+
+def test_matrix_free_rhs_cg_and_guards(gpu):
+    import torch
+    from paper_2406_15959_amd import binding as B
+    P = wl.Problem(3, 3, 60, 10, 10, 8, 6, R=2.0)
+    plan = mfree_plan(P)
+    with pytest.raises(B.ElmddmError) as e:
+        plan.keep_schur(True)
+    assert e.value.status == B.UNSUPPORTED
+    gm = gpu_solve(P, 21, plan=plan)
+    assert gm["info"].status == 0
+    dense = B.Plan(to_c_problem(P))
+    gd = gpu_solve(P, 21, plan=dense)
+    s = plan.sizes
+    dev = torch.device("cuda:0")
+    alphas = wl.fourier_coeffs(9, modes=6, count=3)
+    ipts = plan.points(B.POINTS_INTERIOR)
+    f = torch.from_numpy(wl.fourier_source(alphas, ipts[:, 0], ipts[:, 1])).to(dev)
+    nG = s.n_interface
+    um, ud = [torch.zeros(3 * nG, dtype=torch.float64, device=dev) for _ in range(2)]
+    for p in (plan, dense):
+        p.reserve_rhs(2)
+    plan.solve_rhs(3, f, None, um)
+    dense.solve_rhs(3, f, None, ud)
+    torch.cuda.synchronize()
+    assert rel(um.cpu().numpy(), ud.cpu().numpy()) <= 1e-9
+    rhs = torch.zeros(3 * nG, dtype=torch.float64, device=dev)
+    plan.schur_rhs(3, f, None, rhs)
+    guess = um.clone()
+    st, its = plan.interface_cg(3, rhs, guess, 1e-10, 1000)
+    assert st == B.OK and max(its) <= 1
+    with pytest.raises(B.ElmddmError) as e:
+        B.Graph([(plan, dict(W=torch.from_numpy(gm["W"]).to(dev), b=torch.from_numpy(gm["b"]).to(dev),
+                              f=torch.zeros(s.nsub * s.n_interior, dtype=torch.float64, device=dev),
+                              g=torch.zeros(s.n_boundary, dtype=torch.float64, device=dev), coef=None,
+                              u_gamma=torch.zeros(nG, dtype=torch.float64, device=dev),
+                              c=torch.zeros(s.nsub * s.neurons, dtype=torch.float64, device=dev)))])
+    assert e.value.status == B.UNSUPPORTED
+
+
+def test_five_pass_factorisation_matches_oracle(gpu):
+    from paper_2406_15959_amd import binding as B
+    P = wl.Problem(4, 3, 130, 13, 12, 12, 17, R=2.5)
+    plan = B.Plan(to_c_problem(P))
+    plan.set_passes(5)
+    g = gpu_solve(P, 9, plan=plan)
+    o = oracle_solve(P, 9)
+    assert g["info"].status == 0
+    assert rel(g["u_gamma"], o["u_gamma"]) <= TOL_FP64
+    assert rel(g["uh"], o["uh"]) <= TOL_FP64

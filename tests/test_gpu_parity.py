@@ -255,7 +255,7 @@ def test_four_pass_factorisation_matches_oracle(gpu, mode, tol):
     assert rel(g["u_gamma"], o["u_gamma"]) <= tol
     assert rel(g["uh"], o["uh"]) <= tol
     with pytest.raises(B.ElmddmError):
-        plan.set_passes(5)
+        plan.set_passes(6)
 
 
 @pytest.mark.slow

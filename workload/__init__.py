@@ -75,6 +75,13 @@ CONFIG_8x8 = Problem(nsub_x=8, nsub_y=8, neurons=400, q_x=40, q_y=40,
                      m_bdry_edge=40, m_ifc_edge=40, R=4.0)
 
 
+# The 32x32 case: 1000 neurons per subdomain (U[-sqrt(1000)/5, +]), 64x64
+# interior points, 64 points per edge (126976 interface unknowns), variable
+# coefficient with k1 = 2, k2 = 3.
+CONFIG_32x32 = Problem(nsub_x=32, nsub_y=32, neurons=1000, q_x=64, q_y=64, m_bdry_edge=64, m_ifc_edge=64,
+                       op=OP_VARCOEF, R=math.sqrt(1000.0) / 5.0, k1=2, k2=3)
+
+
 def hidden_params(problem: Problem, seed: int):
     """Random hidden layer of every local network.
 
