@@ -195,7 +195,12 @@ void cg_step(hipStream_t st, int n, double* x, double* r, double* p, const doubl
 // Matrix-free interface operator pieces.
 void mf_tpart(hipStream_t st, int NT, int ngeo, int kpad, const double* P, int ldp, long long sP,
               const int32_t* gidx, const double* v, long long nG, double* t, long long sT, bool shared);
-void mf_mv(hipStream_t st, int nE, int mg, const int32_t* mstart, const int32_t* mE, const double* Mbuf,
-           long long sM, const double* v, long long nG, double* w, long long sW, int ninst);
+
+void transpose_blocks(hipStream_t st, long long nblocks, int mg, const double* Mb, double* MbT);
+void mf_mv4(hipStream_t st, int nE, int mg, const int32_t* mstart, const int32_t* mE, const double* Mbuf,
+            long long sM, const double* v, long long nG, double* w, long long sW, int ninst);
+void mf_mtv4(hipStream_t st, int nE, int mg, const int32_t* qdesc, const int32_t* gptr, const int32_t* gdesc,
+             const double* t, int kpad, const double* MbT, long long sM, const double* w, long long sW, double* y,
+             long long nG, int ngeo, int ninst);
 
 }  // namespace elmddm

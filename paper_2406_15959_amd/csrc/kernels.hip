@@ -1891,8 +1891,8 @@ void cg_step(hipStream_t st, int n, double* x, double* r, double* p, const doubl
 // Matrix-free interface operator (Section 3, eq. schur, applied without
 // forming S):  S v = sum_s R_s^T (I - T_s) R_s v + M^T M v, with T_s the
 // Y^T Y block of the Schur products P_s and M given by its nonzero blocks
-// M_{g,E} (flux edge g x value edge E).  The sum over owners and the M^T w
-// part are done by schur_rhs_kernel on the outputs of these two kernels.
+// M_{g,E} (flux edge g x value edge E), stored column-major mg x mg
+// (element (p, r) at r * mg + p) and, for M^T, transposed.
 // ---------------------------------------------------------------------------
 namespace elmddm {
 
@@ -1926,29 +1926,6 @@ __global__ __launch_bounds__(256) void mf_tpart_kernel(int kpad, const double* P
     }
 }
 
-// w_g = -sum_{E in adj(g)} M_{g,E} v_E for every flux edge g (blocks stored
-// column-major mg x mg: element (p, r) at r * mg + p).  One 64-thread group
-// per edge; mstart[g] .. mstart[g+1] are g's blocks, mE their value edges.
-__global__ void mf_mv_kernel(int mg, const int32_t* mstart, const int32_t* mE, const double* Mbuf,
-                             long long sM, const double* v, long long nG, double* w, long long sW)
-{
-    const int g = blockIdx.x;
-    const long long inst = blockIdx.y;
-    Mbuf += inst * sM;
-    v += inst * nG;
-    w += inst * sW;
-    const int mm = mg * mg;
-    for (int p = threadIdx.x; p < mg; p += blockDim.x) {
-        double acc = 0.0;
-        for (int it = mstart[g]; it < mstart[g + 1]; ++it) {
-            const double* Mb = Mbuf + (long long)it * mm;
-            const double* vE = v + (long long)mE[it] * mg;
-            for (int r = 0; r < mg; ++r) acc += Mb[(long long)r * mg + p] * vE[r];
-        }
-        w[(long long)g * mg + p] = -acc;
-    }
-}
-
 void mf_tpart(hipStream_t st, int NT, int ngeo, int kpad, const double* P, int ldp, long long sP,
               const int32_t* gidx, const double* v, long long nG, double* t, long long sT, bool shared)
 {
@@ -1957,11 +1934,109 @@ void mf_tpart(hipStream_t st, int NT, int ngeo, int kpad, const double* P, int l
                        v, nG, t, sT, ngeo, shared);
 }
 
-void mf_mv(hipStream_t st, int nE, int mg, const int32_t* mstart, const int32_t* mE, const double* Mbuf,
-           long long sM, const double* v, long long nG, double* w, long long sW, int ninst)
+
+}  // namespace elmddm
+
+namespace elmddm {
+
+// MbT[b][p * mg + r] = Mb[b][r * mg + p]: the M blocks transposed, so that
+// M^T w reads them with consecutive lanes on consecutive addresses.
+__global__ __launch_bounds__(256) void transpose_blocks_kernel(int mg, const double* Mb, double* MbT)
+{
+    __shared__ double tile[64][65];
+    const long long b = blockIdx.x;
+    const int mm = mg * mg;
+    const double* src = Mb + b * mm;
+    double* dst = MbT + b * mm;
+    for (int i = threadIdx.x; i < mm; i += 256) tile[i / mg][i % mg] = src[i];
+    __syncthreads();
+    for (int i = threadIdx.x; i < mm; i += 256) dst[i] = tile[i % mg][i / mg];
+}
+
+void transpose_blocks(hipStream_t st, long long nblocks, int mg, const double* Mb, double* MbT)
+{
+    if (nblocks <= 0) return;
+    hipLaunchKernelGGL(transpose_blocks_kernel, dim3((unsigned)nblocks), dim3(256), 0, st, mg, Mb, MbT);
+}
+
+// w_g = -sum_{E in adj(g)} M_{g,E} v_E: four waves per flux edge share its
+// blocks, lane p accumulates row p, the waves' partial sums meet in LDS.
+__global__ __launch_bounds__(256) void mf_mv4_kernel(int mg, const int32_t* mstart, const int32_t* mE,
+                                                     const double* Mbuf, long long sM, const double* v,
+                                                     long long nG, double* w, long long sW)
+{
+    __shared__ double part[4][64];
+    const int g = blockIdx.x;
+    const long long inst = blockIdx.y;
+    Mbuf += inst * sM;
+    v += inst * nG;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int mm = mg * mg;
+    double acc = 0.0;
+    if (lane < mg)
+        for (int it = mstart[g] + wv; it < mstart[g + 1]; it += 4) {
+            const double* Mb = Mbuf + (long long)it * mm;
+            const double* vE = v + (long long)mE[it] * mg;
+            for (int r = 0; r < mg; ++r) acc += Mb[(long long)r * mg + lane] * vE[r];
+        }
+    part[wv][lane] = acc;
+    __syncthreads();
+    if (wv == 0 && lane < mg)
+        w[inst * sW + (long long)g * mg + lane] = -(part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane]);
+}
+
+// y_E = sum over the owners o of E of t_o[slot + r] - sum_{(b, g) in gl(E)} M_b^T w_g
+// (w holds -M v, so this is (I - T) v + M^T M v for the edge): four waves per
+// value edge share its blocks (transposed copies: coalesced), LDS reduction.
+__global__ __launch_bounds__(256) void mf_mtv4_kernel(int mg, const int32_t* qdesc, const int32_t* gptr,
+                                                      const int32_t* gdesc, const double* t, int kpad,
+                                                      const double* MbT, long long sM, const double* w,
+                                                      long long sW, double* y, long long nG, int ngeo,
+                                                      bool shared_t)
+{
+    __shared__ double part[4][64];
+    const int E = blockIdx.x;
+    const long long inst = blockIdx.y;
+    MbT += inst * sM;
+    w += inst * sW;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int mm = mg * mg;
+    double acc = 0.0;
+    if (lane < mg)
+        for (int it = gptr[E] + wv; it < gptr[E + 1]; it += 4) {
+            const double* Mb = MbT + (long long)gdesc[2 * it] * mm;
+            const double* wg = w + (long long)gdesc[2 * it + 1] * mg;
+            for (int p = 0; p < mg; ++p) acc += Mb[(long long)p * mg + lane] * wg[p];
+        }
+    part[wv][lane] = acc;
+    __syncthreads();
+    if (wv == 0 && lane < mg) {
+        double v = -(part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane]);
+        const int32_t* q = qdesc + 4 * E;
+        for (int k = 0; k < 2; ++k) {
+            const int s = q[2 * k];
+            if (s < 0) continue;
+            v += t[(inst * ngeo + s) * (long long)kpad + q[2 * k + 1] + lane];
+        }
+        y[inst * nG + (long long)E * mg + lane] = v;
+    }
+    (void)shared_t;
+}
+
+void mf_mv4(hipStream_t st, int nE, int mg, const int32_t* mstart, const int32_t* mE, const double* Mbuf,
+            long long sM, const double* v, long long nG, double* w, long long sW, int ninst)
 {
     if (nE <= 0) return;
-    hipLaunchKernelGGL(mf_mv_kernel, dim3(nE, ninst), dim3(64), 0, st, mg, mstart, mE, Mbuf, sM, v, nG, w, sW);
+    hipLaunchKernelGGL(mf_mv4_kernel, dim3(nE, ninst), dim3(256), 0, st, mg, mstart, mE, Mbuf, sM, v, nG, w, sW);
+}
+
+void mf_mtv4(hipStream_t st, int nE, int mg, const int32_t* qdesc, const int32_t* gptr, const int32_t* gdesc,
+             const double* t, int kpad, const double* MbT, long long sM, const double* w, long long sW, double* y,
+             long long nG, int ngeo, int ninst)
+{
+    if (nE <= 0) return;
+    hipLaunchKernelGGL(mf_mtv4_kernel, dim3(nE, ninst), dim3(256), 0, st, mg, qdesc, gptr, gdesc, t, kpad, MbT, sM,
+                       w, sW, y, nG, ngeo, false);
 }
 
 }  // namespace elmddm

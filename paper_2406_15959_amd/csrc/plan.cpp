@@ -112,6 +112,7 @@ struct elmddm_plan {
     std::vector<int32_t> cg_iters;
     std::vector<double> cg_relres;
     bool cg_failed = false;
+    double *MbT = nullptr;   // transposed M blocks (matrix-free operator)
     double *tbuf = nullptr, *wbuf = nullptr, *mfX = nullptr, *mfR = nullptr, *mfP = nullptr, *mfQ = nullptr,
            *mfS = nullptr;
     int32_t *d_mstart = nullptr, *d_mE = nullptr, *d_ident = nullptr;
@@ -571,6 +572,7 @@ elmddm_status build(elmddm_plan* P)
         TRY(P->upload(&P->d_mE, mE));
         TRY(P->upload(&P->d_ident, ident));
         TRY(P->dalloc(&P->tbuf, NT * std::max(P->kpad, 1)));
+        TRY(P->dalloc(&P->MbT, Bn * std::max(P->n_mblocks, 1) * mg * mg));
         TRY(P->dalloc(&P->wbuf, Bn * std::max(P->nE, 1) * mg));
         for (double** q : {&P->mfX, &P->mfR, &P->mfP, &P->mfQ}) TRY(P->dalloc(q, Bn * nGm));
         TRY(P->dalloc(&P->mfS, 4 * Bn));
@@ -835,9 +837,9 @@ void apply_mfree(elmddm_plan* P, hipStream_t st, const double* x, double* y, int
     const int N = P->N;
     const long long sM = shared ? 0 : (long long)P->n_mblocks * P->mg * P->mg;
     mf_tpart(st, N * R, N, P->kpad, P->P, P->ldp, P->sP, P->d_gidx, x, P->nG, cb.t, P->kpad, shared);
-    mf_mv(st, P->nE, P->mg, P->d_mstart, P->d_mE, P->Mbuf, sM, x, P->nG, cb.w, (long long)P->nE * P->mg, R);
-    schur_rhs(st, P->nE, P->mg, P->d_qdesc, P->d_gptr, P->d_gdesc, cb.t, 1, P->kpad, 0, P->Mbuf, cb.w, y, 1,
-              P->d_ident, N, sM, (long long)P->nE * P->mg, P->nG, R);
+    mf_mv4(st, P->nE, P->mg, P->d_mstart, P->d_mE, P->Mbuf, sM, x, P->nG, cb.w, (long long)P->nE * P->mg, R);
+    mf_mtv4(st, P->nE, P->mg, P->d_qdesc, P->d_gptr, P->d_gdesc, cb.t, P->kpad, P->MbT, sM, cb.w,
+            (long long)P->nE * P->mg, y, P->nG, N, R);
 }
 
 // CG (stop at ||b - S x|| <= tol ||b||) for R systems on the matrix-free
@@ -979,6 +981,7 @@ elmddm_status elmddm_solve(elmddm_plan* P, const double* W, const double* b, con
                       P->Mbuf, P->abuf, P->yvec, 1, P->d_ident, P->N, sM, (long long)P->nE * P->mg, P->nG, B);
             P->mark(5, st);
             P->mark(6, st);
+            transpose_blocks(st, (long long)B * P->n_mblocks, P->mg, P->Mbuf, P->MbT);
             est = check_launch("Schur pieces");
             if (est != ELMDDM_OK) return est;
             if (hipMemsetAsync(P->mfX, 0, (size_t)B * P->nG * sizeof(double), st) != hipSuccess)
