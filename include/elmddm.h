@@ -156,6 +156,12 @@ int32_t elmddm_plan_is_matrix_free(const elmddm_plan* plan);
  * at most maxit iterations. */
 elmddm_status elmddm_plan_set_cg(elmddm_plan* plan, double tol, int32_t maxit);
 
+/* Preconditioner of that CG: 1 (default) block-Jacobi on the interface edges
+ * (each mg x mg diagonal block S_EE = sum over the edge's two owners of
+ * I - T_s[E, E] plus sum_g M_{g,E}^T M_{g,E}, Cholesky-factored in the
+ * solve), 0 none (the paper's plain CG). */
+elmddm_status elmddm_plan_set_cg_precond(elmddm_plan* plan, int32_t kind);
+
 /* Iterations and final relative residuals (recurrence) of the last CG run on a
  * matrix-free plan, per instance (host arrays of batch entries). */
 elmddm_status elmddm_plan_cg_stats(const elmddm_plan* plan, int32_t* iters, double* relres);

@@ -43,7 +43,7 @@ EXPORTED = [
     "elmddm_mlp_get_params", "elmddm_mlp_forward", "elmddm_mlp_loss_grad", "elmddm_mlp_adam_step",
     "elmddm_mlp_train", "elmddm_mlp_predict",
     "elmddm_plan_query", "elmddm_plan_create_ex", "elmddm_plan_is_matrix_free", "elmddm_plan_set_cg",
-    "elmddm_plan_cg_stats", "elmddm_graph_capture", "elmddm_graph_launch", "elmddm_graph_info",
+    "elmddm_plan_cg_stats", "elmddm_plan_set_cg_precond", "elmddm_graph_capture", "elmddm_graph_launch", "elmddm_graph_info",
     "elmddm_graph_destroy",
     "elmddm_status_string", "elmddm_last_error",
 ]
@@ -123,6 +123,7 @@ def lib():
         L.elmddm_plan_create_ex.argtypes = [ctypes.POINTER(Problem), i32, ctypes.c_uint32, ctypes.POINTER(vp)]
         L.elmddm_plan_is_matrix_free.argtypes = [vp]
         L.elmddm_plan_set_cg.argtypes = [vp, ctypes.c_double, i32]
+        L.elmddm_plan_set_cg_precond.argtypes = [vp, i32]
         L.elmddm_plan_cg_stats.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
         L.elmddm_graph_capture.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(SolveArgs), i32, ctypes.POINTER(vp)]
         L.elmddm_graph_launch.argtypes = [vp, vp]
@@ -296,6 +297,10 @@ class Plan:
 
     def set_cg(self, tol, maxit):
         _check(lib().elmddm_plan_set_cg(self._h, tol, maxit))
+
+    def set_cg_precond(self, kind):
+        """1: block-Jacobi on the interface edges (default), 0: plain CG."""
+        _check(lib().elmddm_plan_set_cg_precond(self._h, kind))
 
     def cg_stats(self):
         """(iterations, relative residuals) of the last CG per instance (matrix-free plans)."""

@@ -203,4 +203,16 @@ void mf_mtv4(hipStream_t st, int nE, int mg, const int32_t* qdesc, const int32_t
              const double* t, int kpad, const double* MbT, long long sM, const double* w, long long sW, double* y,
              long long nG, int ngeo, int ninst);
 
+// Block-Jacobi preconditioned CG on the interface system.
+void mf_diag_blocks(hipStream_t st, int nE, int mg, const int32_t* qdesc, const int32_t* gptr, const int32_t* gdesc,
+                    const double* P, int ldp, long long sP, const double* Mbuf, long long sM, double* D, int ngeo,
+                    int ninst);
+void mf_bjacobi(hipStream_t st, int nE, int mg, const double* Dinv, long long sD, const double* r, double* z,
+                long long nG, int ninst);
+void pcg_init1(hipStream_t st, int n, const double* b, const double* q, double* r, double* state, int nrhs);
+void pcg_init2(hipStream_t st, int n, const double* r, const double* z, double* p, double* state, double tol, int nrhs);
+void pcg_step1(hipStream_t st, int n, double* x, double* r, const double* p, const double* q, double* state,
+               double tol, int nrhs);
+void pcg_step2(hipStream_t st, int n, const double* r, const double* z, double* p, double* state, int nrhs);
+
 }  // namespace elmddm

@@ -956,7 +956,7 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* A, int lda, lon
     }
     __syncthreads();
     if (tid == 0 && bad_any && info) {
-        if (pass <= 3) {
+        if (pass >= 1) {   // a local CholeskyQR pass; pass < 1: the interface matrix
             atomicMin(&info->bad_subdomain, z);
             atomicMax(&info->bad_pass, pass);
             atomicCAS(&info->status, 0, 3);   // ELMDDM_NOT_SPD
@@ -2037,6 +2037,218 @@ void mf_mtv4(hipStream_t st, int nE, int mg, const int32_t* qdesc, const int32_t
     if (nE <= 0) return;
     hipLaunchKernelGGL(mf_mtv4_kernel, dim3(nE, ninst), dim3(256), 0, st, mg, qdesc, gptr, gdesc, t, kpad, MbT, sM,
                        w, sW, y, nG, ngeo, false);
+}
+
+}  // namespace elmddm
+
+// ---------------------------------------------------------------------------
+// Block-Jacobi preconditioner of the interface system: the diagonal edge
+// blocks S_EE = sum_{owners s} (I - T_s[E, E]) + sum_{g: E in adj(g)}
+// M_{g,E}^T M_{g,E} (mg x mg), factored by the 64 x 64 diagonal Cholesky
+// kernel, applied as z_E = L_E^{-T} L_E^{-1} r_E.  PCG recurrences with the
+// state {rz, bb, done, iterations, rr} per system.
+// ---------------------------------------------------------------------------
+namespace elmddm {
+
+__global__ __launch_bounds__(256) void mf_diag_blocks_kernel(int mg, const int32_t* qdesc, const int32_t* gptr,
+                                                             const int32_t* gdesc, const double* P, int ldp,
+                                                             long long sP, const double* Mbuf, long long sM,
+                                                             double* D, int ngeo, int nE)
+{
+    __shared__ double Mb[64][65];
+    const int E = blockIdx.x;
+    const long long inst = blockIdx.y;
+    P += inst * ngeo * sP;
+    Mbuf += inst * sM;
+    double* De = D + (inst * nE + E) * 4096LL;
+    const int mm = mg * mg;
+    double acc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+    // owners: I - T_s on the edge's slots
+    const int32_t* q4 = qdesc + 4 * E;
+    for (int k = 0; k < 2; ++k) {
+        const int s = q4[2 * k];
+        if (s < 0) continue;
+        const int slot = q4[2 * k + 1];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int idx = threadIdx.x + 256 * q;
+            const int r = idx & 63, c = idx >> 6;
+            if (r < mg && c < mg)
+                acc[q] += (r == c ? 1.0 : 0.0) - P[s * sP + (long long)(slot + c) * ldp + slot + r];
+        }
+    }
+    // M^T M on the edge: D[r][c] += sum_p M[p][r] M[p][c]
+    for (int it = gptr[E]; it < gptr[E + 1]; ++it) {
+        const double* M = Mbuf + (long long)gdesc[2 * it] * mm;
+        __syncthreads();
+        for (int i = threadIdx.x; i < mm; i += 256) Mb[i / mg][i % mg] = M[i];   // Mb[r][p] = M(p, r)
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int idx = threadIdx.x + 256 * q;
+            const int r = idx & 63, c = idx >> 6;
+            if (r < mg && c < mg) {
+                double v = 0.0;
+                for (int p = 0; p < mg; ++p) v += Mb[r][p] * Mb[c][p];
+                acc[q] += v;
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int idx = threadIdx.x + 256 * q;
+        const int r = idx & 63, c = idx >> 6;
+        De[idx] = (r < mg && c < mg) ? acc[q] : (r == c ? 1.0 : 0.0);
+    }
+}
+
+void mf_diag_blocks(hipStream_t st, int nE, int mg, const int32_t* qdesc, const int32_t* gptr, const int32_t* gdesc,
+                    const double* P, int ldp, long long sP, const double* Mbuf, long long sM, double* D, int ngeo,
+                    int ninst)
+{
+    if (nE <= 0) return;
+    hipLaunchKernelGGL(mf_diag_blocks_kernel, dim3(nE, ninst), dim3(256), 0, st, mg, qdesc, gptr, gdesc, P, ldp, sP,
+                       Mbuf, sM, D, ngeo, nE);
+}
+
+// z_E = L^{-T} (L^{-1} r_E) with L^{-1} = Dinv (64 x 64 column-major, lower)
+__global__ __launch_bounds__(64) void mf_bjacobi_kernel(int mg, int nE, const double* Dinv, long long sD,
+                                                        const double* r, double* z, long long nG)
+{
+    __shared__ double Li[64][65];
+    __shared__ double y[64];
+    const int E = blockIdx.x;
+    const long long inst = blockIdx.y;
+    const double* Di = Dinv + inst * sD + (long long)E * 4096;
+    const int i = threadIdx.x;
+    for (int k = 0; k < 64; ++k) Li[i][k] = Di[k * 64 + i];   // Li[i][k] = L^{-1}(i, k)
+    const double* rE = r + inst * nG + (long long)E * mg;
+    __syncthreads();
+    double acc = 0.0;
+    if (i < mg)
+        for (int k = 0; k <= i; ++k) acc += Li[i][k] * rE[k];
+    y[i] = acc;
+    __syncthreads();
+    if (i < mg) {
+        double v = 0.0;
+        for (int k = i; k < mg; ++k) v += Li[k][i] * y[k];
+        z[inst * nG + (long long)E * mg + i] = v;
+    }
+}
+
+void mf_bjacobi(hipStream_t st, int nE, int mg, const double* Dinv, long long sD, const double* r, double* z,
+                long long nG, int ninst)
+{
+    if (nE <= 0) return;
+    hipLaunchKernelGGL(mf_bjacobi_kernel, dim3(nE, ninst), dim3(64), 0, st, mg, nE, Dinv, sD, r, z, nG);
+}
+
+// r = b - q (q = S x); rr = r.r, bb = b.b
+__global__ __launch_bounds__(1024) void pcg_init1_kernel(int n, const double* b, const double* q, double* r,
+                                                         double* state)
+{
+    __shared__ double red[16];
+    const long long o = (long long)blockIdx.x * n;
+    double rr = 0.0, bb = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double ri = b[o + i] - q[o + i];
+        r[o + i] = ri;
+        rr += ri * ri;
+        bb += b[o + i] * b[o + i];
+    }
+    rr = block_sum(rr, red);
+    bb = block_sum(bb, red);
+    if (threadIdx.x == 0) {
+        double* s = state + 8 * blockIdx.x;
+        s[1] = bb;
+        s[4] = rr;
+        s[3] = 0.0;
+    }
+}
+
+// p = z; rz = r.z; done if rr <= tol^2 bb
+__global__ __launch_bounds__(1024) void pcg_init2_kernel(int n, const double* r, const double* z, double* p,
+                                                         double* state, double tol)
+{
+    __shared__ double red[16];
+    const long long o = (long long)blockIdx.x * n;
+    double rz = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        p[o + i] = z[o + i];
+        rz += r[o + i] * z[o + i];
+    }
+    rz = block_sum(rz, red);
+    if (threadIdx.x == 0) {
+        double* s = state + 8 * blockIdx.x;
+        s[0] = rz;
+        s[2] = (s[4] <= tol * tol * s[1]) ? 1.0 : 0.0;
+    }
+}
+
+// alpha = rz / p.q; x += alpha p; r -= alpha q; rr = r.r; done if rr <= tol^2 bb
+__global__ __launch_bounds__(1024) void pcg_step1_kernel(int n, double* x, double* r, const double* p,
+                                                         const double* q, double* state, double tol)
+{
+    __shared__ double red[16];
+    double* s = state + 8 * blockIdx.x;
+    if (s[2] != 0.0) return;
+    const long long o = (long long)blockIdx.x * n;
+    double pq = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) pq += p[o + i] * q[o + i];
+    pq = block_sum(pq, red);
+    const double alpha = pq > 0.0 ? s[0] / pq : 0.0;
+    double rr = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        x[o + i] += alpha * p[o + i];
+        const double ri = r[o + i] - alpha * q[o + i];
+        r[o + i] = ri;
+        rr += ri * ri;
+    }
+    rr = block_sum(rr, red);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        s[4] = rr;
+        s[3] += 1.0;
+        if (!(pq > 0.0)) s[2] = 2.0;
+        else if (rr <= tol * tol * s[1]) s[2] = 1.0;
+    }
+}
+
+// rz' = r.z; beta = rz'/rz; p = z + beta p
+__global__ __launch_bounds__(1024) void pcg_step2_kernel(int n, const double* r, const double* z, double* p,
+                                                         double* state)
+{
+    __shared__ double red[16];
+    double* s = state + 8 * blockIdx.x;
+    if (s[2] != 0.0) return;
+    const long long o = (long long)blockIdx.x * n;
+    double rz = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) rz += r[o + i] * z[o + i];
+    rz = block_sum(rz, red);
+    const double beta = s[0] > 0.0 ? rz / s[0] : 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[o + i] = z[o + i] + beta * p[o + i];
+    __syncthreads();
+    if (threadIdx.x == 0) s[0] = rz;
+}
+
+void pcg_init1(hipStream_t st, int n, const double* b, const double* q, double* r, double* state, int nrhs)
+{
+    hipLaunchKernelGGL(pcg_init1_kernel, dim3(nrhs), dim3(1024), 0, st, n, b, q, r, state);
+}
+void pcg_init2(hipStream_t st, int n, const double* r, const double* z, double* p, double* state, double tol, int nrhs)
+{
+    hipLaunchKernelGGL(pcg_init2_kernel, dim3(nrhs), dim3(1024), 0, st, n, r, z, p, state, tol);
+}
+void pcg_step1(hipStream_t st, int n, double* x, double* r, const double* p, const double* q, double* state,
+               double tol, int nrhs)
+{
+    hipLaunchKernelGGL(pcg_step1_kernel, dim3(nrhs), dim3(1024), 0, st, n, x, r, p, q, state, tol);
+}
+void pcg_step2(hipStream_t st, int n, const double* r, const double* z, double* p, double* state, int nrhs)
+{
+    hipLaunchKernelGGL(pcg_step2_kernel, dim3(nrhs), dim3(1024), 0, st, n, r, z, p, state);
 }
 
 }  // namespace elmddm

@@ -113,6 +113,8 @@ struct elmddm_plan {
     std::vector<double> cg_relres;
     bool cg_failed = false;
     double *MbT = nullptr;   // transposed M blocks (matrix-free operator)
+    int cg_precond = 1;      // 0: plain CG (the paper's), 1: block-Jacobi on the edge blocks
+    double *DE = nullptr, *DEinv = nullptr;   // edge blocks of S and their inverse factors
     double *tbuf = nullptr, *wbuf = nullptr, *mfX = nullptr, *mfR = nullptr, *mfP = nullptr, *mfQ = nullptr,
            *mfS = nullptr;
     int32_t *d_mstart = nullptr, *d_mE = nullptr, *d_ident = nullptr;
@@ -575,7 +577,9 @@ elmddm_status build(elmddm_plan* P)
         TRY(P->dalloc(&P->MbT, Bn * std::max(P->n_mblocks, 1) * mg * mg));
         TRY(P->dalloc(&P->wbuf, Bn * std::max(P->nE, 1) * mg));
         for (double** q : {&P->mfX, &P->mfR, &P->mfP, &P->mfQ}) TRY(P->dalloc(q, Bn * nGm));
-        TRY(P->dalloc(&P->mfS, 4 * Bn));
+        TRY(P->dalloc(&P->mfS, 8 * Bn));
+        TRY(P->dalloc(&P->DE, Bn * std::max(P->nE, 1) * 4096));
+        TRY(P->dalloc(&P->DEinv, Bn * std::max(P->nE, 1) * 4096));
     }
     TRY(P->dalloc(&P->yvec, Bn * nGm));
     TRY(P->dalloc(&P->dsave, std::max(NT * n, Bn * nGm)));
@@ -773,6 +777,15 @@ elmddm_status elmddm_plan_set_cg(elmddm_plan* P, double tol, int32_t maxit)
     return ELMDDM_OK;
 }
 
+elmddm_status elmddm_plan_set_cg_precond(elmddm_plan* P, int32_t kind)
+{
+    if (!P) return fail(ELMDDM_INVALID_ARG, "NULL plan");
+    if (kind != 0 && kind != 1) return fail(ELMDDM_INVALID_ARG, "preconditioner kind must be 0 or 1");
+    P->cg_precond = kind;
+    P->factors_valid = false;   // the preconditioner is set up by the next solve
+    return ELMDDM_OK;
+}
+
 elmddm_status elmddm_plan_cg_stats(const elmddm_plan* P, int32_t* iters, double* relres)
 {
     if (!P || !iters || !relres) return fail(ELMDDM_INVALID_ARG, "NULL argument");
@@ -827,7 +840,7 @@ elmddm_status elmddm_get_schur(elmddm_plan* P, double* S, double* rhs, void* str
 namespace {
 
 struct CgBufs {
-    double *r, *p, *q, *state, *t, *w;
+    double *r, *p, *q, *state, *t, *w, *z;
 };
 
 // y = S x for R systems with the matrix-free operator (Section 3, eq. schur
@@ -843,16 +856,27 @@ void apply_mfree(elmddm_plan* P, hipStream_t st, const double* x, double* y, int
 }
 
 // CG (stop at ||b - S x|| <= tol ||b||) for R systems on the matrix-free
-// operator; x holds the start.  Polls the convergence flags every 32 steps.
+// operator, block-Jacobi preconditioned if the plan says so (the inverse
+// edge-block factors of instance 0 serve all systems when shared); x holds
+// the start.  Polls the convergence flags every 32 steps.
 elmddm_status run_cg(elmddm_plan* P, hipStream_t st, const double* b, double* x, int R, double tol, int maxit,
                      bool shared, const CgBufs& cb)
 {
     const int nG = P->nG;
+    const bool pre = P->cg_precond != 0;
+    const long long sD = shared ? 0 : (long long)P->nE * 4096;
     apply_mfree(P, st, x, cb.q, R, shared, cb);
-    cg_init(st, nG, b, cb.q, cb.r, cb.p, cb.state, tol, R);
-    std::vector<double> state(4 * R, 0.0);
+    if (pre) {
+        pcg_init1(st, nG, b, cb.q, cb.r, cb.state, R);
+        mf_bjacobi(st, P->nE, P->mg, P->DEinv, sD, cb.r, cb.z, nG, R);
+        pcg_init2(st, nG, cb.r, cb.z, cb.p, cb.state, tol, R);
+    } else {
+        cg_init(st, nG, b, cb.q, cb.r, cb.p, cb.state, tol, R);
+    }
+    const int ss = pre ? 8 : 4;   // state words per system
+    std::vector<double> state(ss * R, 0.0);
     auto poll = [&]() -> elmddm_status {
-        if (hipMemcpyAsync(state.data(), cb.state, 4 * R * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        if (hipMemcpyAsync(state.data(), cb.state, ss * R * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
             hipStreamSynchronize(st) != hipSuccess)
             return check_launch("CG poll");
         return ELMDDM_OK;
@@ -861,12 +885,18 @@ elmddm_status run_cg(elmddm_plan* P, hipStream_t st, const double* b, double* x,
     if (est != ELMDDM_OK) return est;
     auto all_done = [&]() {
         for (int q = 0; q < R; ++q)
-            if (state[4 * q + 2] == 0.0) return false;
+            if (state[ss * q + 2] == 0.0) return false;
         return true;
     };
     for (int it = 0; it < maxit && !all_done(); ++it) {
         apply_mfree(P, st, cb.p, cb.q, R, shared, cb);
-        cg_step(st, nG, x, cb.r, cb.p, cb.q, cb.state, tol, R);
+        if (pre) {
+            pcg_step1(st, nG, x, cb.r, cb.p, cb.q, cb.state, tol, R);
+            mf_bjacobi(st, P->nE, P->mg, P->DEinv, sD, cb.r, cb.z, nG, R);
+            pcg_step2(st, nG, cb.r, cb.z, cb.p, cb.state, R);
+        } else {
+            cg_step(st, nG, x, cb.r, cb.p, cb.q, cb.state, tol, R);
+        }
         if ((it & 31) == 31 || it + 1 == maxit) {
             est = poll();
             if (est != ELMDDM_OK) return est;
@@ -878,11 +908,22 @@ elmddm_status run_cg(elmddm_plan* P, hipStream_t st, const double* b, double* x,
     P->cg_relres.assign(R, 0.0);
     P->cg_failed = false;
     for (int q = 0; q < R; ++q) {
-        P->cg_iters[q] = (int32_t)state[4 * q + 3];
-        P->cg_relres[q] = state[4 * q + 1] > 0.0 ? std::sqrt(state[4 * q] / state[4 * q + 1]) : 0.0;
-        if (state[4 * q + 2] != 1.0) P->cg_failed = true;
+        const double rr = pre ? state[ss * q + 4] : state[ss * q];
+        P->cg_iters[q] = (int32_t)state[ss * q + 3];
+        P->cg_relres[q] = state[ss * q + 1] > 0.0 ? std::sqrt(rr / state[ss * q + 1]) : 0.0;
+        if (state[ss * q + 2] != 1.0) P->cg_failed = true;
     }
     return check_launch("CG");
+}
+
+// Edge blocks of S and their inverse Cholesky factors (block-Jacobi).
+void setup_bjacobi(elmddm_plan* P, hipStream_t st)
+{
+    const long long sM = (long long)P->n_mblocks * P->mg * P->mg;
+    mf_diag_blocks(st, P->nE, P->mg, P->d_qdesc, P->d_gptr, P->d_gdesc, P->P, P->ldp, P->sP, P->Mbuf, sM, P->DE,
+                   P->N, P->B);
+    potrf_diag(st, P->DE, 64, 4096, 0, P->mg, P->DEinv, 4096, nullptr, 0, 0, P->d_info, -1, P->B * P->nE, nullptr,
+               0, 0.0, nullptr, 0);
 }
 
 }  // namespace
@@ -982,12 +1023,13 @@ elmddm_status elmddm_solve(elmddm_plan* P, const double* W, const double* b, con
             P->mark(5, st);
             P->mark(6, st);
             transpose_blocks(st, (long long)B * P->n_mblocks, P->mg, P->Mbuf, P->MbT);
+            if (P->cg_precond) setup_bjacobi(P, st);
             est = check_launch("Schur pieces");
             if (est != ELMDDM_OK) return est;
             if (hipMemsetAsync(P->mfX, 0, (size_t)B * P->nG * sizeof(double), st) != hipSuccess)
                 return check_launch("CG start");
             est = run_cg(P, st, P->yvec, P->mfX, B, P->cg_tol, P->cg_maxit, false,
-                         CgBufs{P->mfR, P->mfP, P->mfQ, P->mfS, P->tbuf, P->wbuf});
+                         CgBufs{P->mfR, P->mfP, P->mfQ, P->mfS, P->tbuf, P->wbuf, P->uperm});
             if (est != ELMDDM_OK) return est;
             if (hipMemcpyAsync(u_gamma, P->mfX, (size_t)B * P->nG * sizeof(double), hipMemcpyDeviceToDevice, st) !=
                 hipSuccess)
@@ -1010,7 +1052,7 @@ elmddm_status elmddm_solve(elmddm_plan* P, const double* W, const double* b, con
             // block by block, then back to the interface numbering.
             const long long sDS = (long long)P->nblkS * NB * NB;
             envelope_potrf(st, P->Sx, P->lds, sS, P->SL, P->lds, sS, P->nG, P->rend.data(), P->DinvS, sDS,
-                           P->d_info, 4, P->dsave, P->yvec, P->nG, B, P->env_fused);
+                           P->d_info, -1, P->dsave, P->yvec, P->nG, B, P->env_fused);
             P->mark(6, st);
             const int BR = 4 * NB;
             for (int j0 = (P->nG - 1) / BR * BR; j0 >= 0; j0 -= BR) {
@@ -1066,7 +1108,7 @@ elmddm_status elmddm_plan_reserve_rhs(elmddm_plan* P, int32_t max_rhs)
     if ((st = P->dalloc(&P->uR, R * nGm)) != ELMDDM_OK) return st;
     for (double** q : {&P->cgX, &P->cgR, &P->cgP, &P->cgQ})
         if ((st = P->dalloc(q, R * nGm)) != ELMDDM_OK) return st;
-    if ((st = P->dalloc(&P->cgS, 4 * R)) != ELMDDM_OK) return st;
+    if ((st = P->dalloc(&P->cgS, 8 * R)) != ELMDDM_OK) return st;
     if (P->mfree) {
         if ((st = P->dalloc(&P->tbufR, N * R * std::max(P->kpad, 1))) != ELMDDM_OK) return st;
         if ((st = P->dalloc(&P->wbufR, R * std::max(P->nE, 1) * P->mg)) != ELMDDM_OK) return st;
@@ -1135,7 +1177,7 @@ elmddm_status elmddm_solve_rhs(elmddm_plan* P, int32_t nrhs, const double* f, co
             if (hipMemsetAsync(ur, 0, (size_t)R * nG * sizeof(double), st) != hipSuccess)
                 return check_launch("CG start");
             est = run_cg(P, st, P->yR, ur, R, P->cg_tol, P->cg_maxit, true,
-                         CgBufs{P->cgR, P->cgP, P->cgQ, P->cgS, P->tbufR, P->wbufR});
+                         CgBufs{P->cgR, P->cgP, P->cgQ, P->cgS, P->tbufR, P->wbufR, P->uR});
             if (est != ELMDDM_OK) return est;
             if (P->cg_failed) return fail(ELMDDM_NOT_CONVERGED, "interface CG did not reach the tolerance");
         } else if (nG > 0) {
@@ -1206,7 +1248,7 @@ elmddm_status elmddm_interface_cg(elmddm_plan* P, int32_t nrhs, const double* rh
                 hipMemcpyAsync(P->cgX, u + (long long)r0 * nG, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess)
                 return check_launch("interface_cg copy");
             elmddm_status est = run_cg(P, st, P->yR, P->cgX, R, tol, maxit, true,
-                                       CgBufs{P->cgR, P->cgP, P->cgQ, P->cgS, P->tbufR, P->wbufR});
+                                       CgBufs{P->cgR, P->cgP, P->cgQ, P->cgS, P->tbufR, P->wbufR, P->uR});
             if (est != ELMDDM_OK) return est;
             for (int q = 0; q < R; ++q) {
                 if (iters) iters[r0 + q] = P->cg_iters[q];

@@ -124,3 +124,16 @@ def test_five_pass_factorisation_matches_oracle(gpu):
     assert g["info"].status == 0
     assert rel(g["u_gamma"], o["u_gamma"]) <= TOL_FP64
     assert rel(g["uh"], o["uh"]) <= TOL_FP64
+
+
+@pytest.mark.parametrize("P,seed", [(wl.CONFIG_8x8, 2004), (wl.Problem(4, 4, 80, 12, 12, 12, 8, R=2.0), 3)])
+def test_block_jacobi_pcg_equals_plain_cg_with_fewer_iterations(gpu, P, seed):
+    plan = mfree_plan(P)
+    g1 = gpu_solve(P, seed, plan=plan)
+    it1, _ = plan.cg_stats()
+    plan.set_cg_precond(0)
+    g0 = gpu_solve(P, seed, plan=plan)
+    it0, _ = plan.cg_stats()
+    assert g1["info"].status == 0 and g0["info"].status == 0
+    assert rel(g1["u_gamma"], g0["u_gamma"]) <= 1e-9
+    assert it1[0] < it0[0], (it1, it0)
