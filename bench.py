@@ -34,24 +34,78 @@ HBM_PEAK_GBS = 8000.0
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "gram_8x8_fp64_batch8_pmc.txt")
 
 
+def gram_source_sha():
+    """sha256 of the source of the Gram candidates (the MFMA GEMM and strip
+    kernels of kernels.hip, from the GEMM banner to strip_width)."""
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_2406_15959_amd", "csrc", "kernels.hip")).read()
+    a = src.index("// Batched GEMM on the matrix cores")
+    b = src.index("int strip_width(int n)")
+    return hashlib.sha256(src[a:b].encode()).hexdigest()
+
+
 def measured_traffic(gram_code, batch):
     """HBM bytes per Gram launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
     summary (one entry per autotuner candidate), if it was taken with this kernel
     source and batch; else None."""
-    import hashlib
     try:
         kv = {}
         for line in open(PMC_SUMMARY):
             if ":" in line:
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-        src = os.path.join(ROOT, "paper_2406_15959_amd", "csrc", "kernels.hip")
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        if kv.get("kernels_hip_sha256") != sha or int(kv["batch"]) != batch:
+        if kv.get("gram_kernels_sha256") != gram_source_sha() or int(kv["batch"]) != batch:
             return None
         return float(kv["traffic_bytes_per_launch[%d]" % gram_code])
     except (OSError, KeyError, ValueError):
         return None
+
+
+def mfma_ceilings(torch):
+    """Register-only rates of the FP64 matrix instructions on this device
+    (TFLOP/s), measured by the test-hooks library: the ceiling of any kernel
+    built on each instruction, beside the published dense FP64 peak."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_2406_15959_amd", "libelmddm_testhooks.so")
+    if not os.path.exists(path):
+        return None
+    L = ctypes.CDLL(path)
+    L.elmddm_test_mfma_f64_rate.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                            ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    out = {"unit": "TFLOP/s", "how": "MFMA loop from registers only, every SIMD busy (test-hooks library)"}
+    for name, shape, waves in (("mfma_f64_16x16x4", 0, 4), ("mfma_f64_4x4x4_4b", 1, 4)):
+        r = ctypes.c_double()
+        if L.elmddm_test_mfma_f64_rate(shape, waves, 4000, ctypes.byref(r), st) != 0:
+            return None
+        out[name] = r.value
+    return out
+
+
+def library_gram_reference(torch, batch, rows, n, reps=5):
+    """The vendor library on the same Gram shape, for context: torch.bmm in
+    FP64 (rocBLAS / hipBLASLt strided-batched DGEMM) forming the full
+    n x n product X^T X of `batch` random rows x n matrices (twice the flops
+    of the lower triangle the hot path computes).  Not used by the path."""
+    g = torch.Generator(device="cuda").manual_seed(7)
+    X = torch.randn(batch, rows, n, dtype=torch.float64, device="cuda", generator=g)
+    Xt = X.transpose(1, 2).contiguous()
+    out = torch.empty(batch, n, n, dtype=torch.float64, device="cuda")
+    torch.bmm(Xt, X, out=out)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.bmm(Xt, X, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    full = 2.0 * batch * rows * n * n
+    res = {"op": "torch.bmm FP64 X^T X, full product (vendor strided-batched DGEMM)",
+           "shape": [batch, n, rows, n], "ms": ms, "tflops_full_product": full / (ms * 1e-3) / 1e12,
+           "ms_per_lower_triangle_equivalent": ms * (n + 1) / (2.0 * n)}
+    del X, Xt, out
+    torch.cuda.empty_cache()
+    return res
 
 
 def learned_leg(B, wl, torch, log):
@@ -455,6 +509,13 @@ def main():
                              "achieved": flops_per_launch / (gram32_ms * 1e-3) / 1e12 if gram32_ms > 0 else 0.0,
                              "peak": MFMA_F32_PEAK_TFLOPS, "unit": "TFLOP/s", "avg_launch_ms": gram32_ms}}
     roofline["f32_gram"]["frac"] = roofline["f32_gram"]["achieved"] / MFMA_F32_PEAK_TFLOPS
+    # The Gram kernels are built on V_MFMA_F64_16X16X4, whose sustained rate
+    # on this device is well below the published FP64 peak: report it too.
+    ceil = mfma_ceilings(torch)
+    roofline["instruction_ceiling"] = ceil
+    roofline["library_reference"] = library_gram_reference(torch, nb * P.nsub, m_rows, n)
+    if ceil:
+        roofline["frac_of_instruction_ceiling"] = achieved / ceil["mfma_f64_16x16x4"]
     learned_out = ragged_out = None
     del plan, inst, df, dg, du, dc
     torch.cuda.empty_cache()

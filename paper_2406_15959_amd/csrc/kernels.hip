@@ -660,11 +660,11 @@ void trsm_strip(hipStream_t st, int T, int rows, int n, const double* X, int ldx
 void gram_product(hipStream_t st, int code, int n, int rows, const double* X, int ldx, long long sX,
                   double* G, int ldg, long long sG, int batch)
 {
+    if (n <= 0 || batch <= 0) return;
     if (code >= 4) {
         gram_strip(st, code, n, rows, X, ldx, sX, G, ldg, sG, batch);
         return;
     }
-    if (n <= 0 || batch <= 0) return;
     gemm_dispatch<true, false, 0, true>(-1 - code, st, n, n, rows, 1.0, X, ldx, sX, X, ldx, sX, 0.0, G,
                                         ldg, sG, batch);
 }

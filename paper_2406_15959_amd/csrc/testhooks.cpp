@@ -81,6 +81,14 @@ int elmddm_test_gram_strip(int n, int rows, const double* X, int ldx, long long 
     return hipGetLastError() == hipSuccess ? 0 : 7;
 }
 
+// Gram product through the autotuner's dispatch: code as in elmddm_autotune.
+int elmddm_test_gram(int code, int n, int rows, const double* X, int ldx, long long sX, double* G, int ldg,
+                     long long sG, int batch, void* stream)
+{
+    gram_product((hipStream_t)stream, code, n, rows, X, ldx, sX, G, ldg, sG, batch);
+    return hipGetLastError() == hipSuccess ? 0 : 7;
+}
+
 int elmddm_test_trsm_strip(int rows, int n, const double* X, int ldx, long long sX, const double* Li,
                            int ldl, long long sL, double* Y, long long sY, int batch, void* stream)
 {
@@ -99,3 +107,81 @@ int elmddm_test_potrf(double* A, int lda, long long sA, int Mrows, int n, double
 }
 
 }  // extern "C"
+
+// Sustained rate of the FP64 matrix instructions from registers alone (no
+// memory traffic in the loop): the ceiling that any kernel built on the
+// instruction can reach on this device, next to the published peak.
+// SHAPE 0: V_MFMA_F64_16X16X4, 8 independent accumulators per wave.
+// SHAPE 1: V_MFMA_F64_4X4X4_4B, a 4 x 4 outer product of operand registers
+// (16 accumulators per wave).  Operands change every iteration so that the
+// loop cannot be folded.
+template <int SHAPE>
+__global__ __launch_bounds__(256) void mfma_rate_kernel(double* out, int iters)
+{
+    double s = 0.0;
+    if (SHAPE == 0) {
+        v4d acc[8];
+        for (int j = 0; j < 8; ++j) acc[j] = (v4d){0.0, 0.0, 0.0, 0.0};
+        double a = threadIdx.x * 1e-3, b = 1.0 + blockIdx.x * 1e-6;
+        for (int i = 0; i < iters; ++i) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[j], 0, 0, 0);
+            a = __shfl_xor(a, 1);
+        }
+        for (int j = 0; j < 8; ++j) s += acc[j][0] + acc[j][1] + acc[j][2] + acc[j][3];
+    } else {
+        double acc[16], a[4], b[4];
+        for (int j = 0; j < 16; ++j) acc[j] = 0.0;
+        for (int j = 0; j < 4; ++j) {
+            a[j] = threadIdx.x * 1e-3 + j;
+            b[j] = 1.0 + blockIdx.x * 1e-6 + j;
+        }
+        for (int i = 0; i < iters; ++i) {
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    acc[4 * p + q] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[p], b[q], acc[4 * p + q], 0, 0, 0);
+#pragma unroll
+            for (int p = 0; p < 4; ++p) a[p] = __shfl_xor(a[p], 1);
+        }
+        for (int j = 0; j < 16; ++j) s += acc[j];
+    }
+    out[(size_t)blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
+// Runs the loop above with waves_per_simd waves on every SIMD of the device
+// (workgroups of four waves, one per SIMD) and returns the rate in TFLOP/s
+// (*tflops) measured with events on stream.  Returns 0, or 7 on a HIP error.
+extern "C" int elmddm_test_mfma_f64_rate(int shape, int waves_per_simd, int iters, double* tflops, void* stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 7;
+    const int blocks = cus * waves_per_simd;
+    double* out = nullptr;
+    if (hipMalloc(&out, sizeof(double) * blocks * 256) != hipSuccess) return 7;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return 7;
+    auto launch = [&] {
+        if (shape == 0) hipLaunchKernelGGL(mfma_rate_kernel<0>, dim3(blocks), dim3(256), 0, st, out, iters);
+        else hipLaunchKernelGGL(mfma_rate_kernel<1>, dim3(blocks), dim3(256), 0, st, out, iters);
+    };
+    launch();
+    (void)hipEventRecord(e0, st);
+    launch();
+    (void)hipEventRecord(e1, st);
+    (void)hipEventSynchronize(e1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    const double flops_per_inst = shape == 0 ? 2.0 * 16 * 16 * 4 : 2.0 * 4 * 4 * 4 * 4;
+    const double insts = (double)blocks * 4 * iters * (shape == 0 ? 8 : 16);
+    *tflops = insts * flops_per_inst / (ms * 1e-3) / 1e12;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    const bool ok = hipGetLastError() == hipSuccess;
+    (void)hipFree(out);
+    return ok ? 0 : 7;
+}

@@ -26,6 +26,7 @@ def hooks(gpu):
     L.elmddm_test_potrf.argtypes = [vp, i32, i64, i32, i32, vp, i64, vp, i32, i64, vp, vp, i32, vp]
     L.elmddm_test_mfma_layout_f32.argtypes = [vp, vp, vp, vp]
     L.elmddm_test_gram_f32.argtypes = [i32, i32, vp, i32, i64, vp, i32, i64, i32, vp]
+    L.elmddm_test_gram.argtypes = [i32, i32, i32, vp, i32, i64, vp, i32, i64, i32, vp]
     return L
 
 
@@ -244,6 +245,37 @@ def test_gram_strip_lower_triangle(hooks, n, rows, batch):
         got = G[z, :n, :n].T                         # back to row-major math orientation
         mask = np.tril(np.ones((n, n), bool))
         assert np.abs(np.where(mask, got - ref, 0)).max() <= 1e-13 * np.abs(ref).max()
+
+
+GRAM_CODES = [-1, -2, -3, -4, 4, 5, 6, 7, 8]
+
+
+@pytest.mark.parametrize("code", GRAM_CODES)
+@pytest.mark.parametrize("n,rows,batch", [(400, 1920, 3), (130, 71, 2), (257, 300, 1), (16, 5, 2), (1, 9, 2)])
+def test_gram_candidates_lower_triangle_and_bounds(hooks, code, n, rows, batch):
+    """Every Gram candidate of the autotuner gives the lower triangle of X^T X
+    and writes nothing outside the n x n block of each matrix (sentinel
+    padding in the leading dimension, the extra column and between
+    batch entries stays)."""
+    import torch
+    rng = np.random.default_rng(1000 * n + rows + code)
+    ldx, ldg = rows + 3, n + 7
+    X = rng.standard_normal((batch, n + 1, ldx))
+    dX = _dev(X)
+    sentinel = 12345.0
+    dG = torch.full((batch * (n + 1) * ldg,), sentinel, dtype=torch.float64, device="cuda:0")
+    st = hooks.elmddm_test_gram(code, n, rows, _p(dX), ldx, (n + 1) * ldx, _p(dG), ldg, (n + 1) * ldg, batch,
+                                _stream())
+    assert st == 0
+    torch.cuda.synchronize()
+    G = dG.cpu().numpy().reshape(batch, n + 1, ldg)
+    mask = np.tril(np.ones((n, n), bool))
+    for z in range(batch):
+        Xz = X[z, :n, :rows].T
+        ref = Xz.T @ Xz
+        got = G[z, :n, :n].T
+        assert np.abs(np.where(mask, got - ref, 0)).max() <= 1e-13 * np.abs(ref).max()
+        assert np.all(G[z, :n, n:] == sentinel) and np.all(G[z, n, :] == sentinel)
 
 
 @pytest.mark.parametrize("rows,n,batch", [(2016, 400, 2), (480, 100, 3), (70, 30, 2), (333, 200, 1)])

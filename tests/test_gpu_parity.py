@@ -224,6 +224,8 @@ def test_autotuned_kernels_and_split_envelope_path_match_oracle(gpu):
     plan = B.Plan(to_c_problem(P), batch=nb)
     codes = plan.autotune()
     assert len(codes) == 2 and all(c < 0 or 4 <= c <= 8 for c in codes)
+    times = plan.autotune_times()
+    assert sorted(times) == [-4, -3, -2, -1, 4, 5, 6, 7, 8] and all(g > 0 and t > 0 for g, t in times.values())
     s = plan.sizes
     f, g, _ = wl.sample_data(P, plan.points(B.POINTS_INTERIOR), plan.points(B.POINTS_BOUNDARY))
     seeds = [41, 42, 43, 44]
