@@ -74,11 +74,14 @@ def mfma_ceilings(torch):
                                             ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]
     st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     out = {"unit": "TFLOP/s", "how": "MFMA loop from registers only, every SIMD busy (test-hooks library)"}
-    for name, shape, waves in (("mfma_f64_16x16x4", 0, 4), ("mfma_f64_4x4x4_4b", 1, 4)):
-        r = ctypes.c_double()
-        if L.elmddm_test_mfma_f64_rate(shape, waves, 4000, ctypes.byref(r), st) != 0:
-            return None
-        out[name] = r.value
+    for name, shape in (("mfma_f64_16x16x4", 0), ("mfma_f64_4x4x4_4b", 1)):
+        best = 0.0
+        for waves in (2, 4, 8):   # best of three occupancies
+            r = ctypes.c_double()
+            if L.elmddm_test_mfma_f64_rate(shape, waves, 2000, ctypes.byref(r), st) != 0:
+                return None
+            best = max(best, r.value)
+        out[name] = best
     return out
 
 
@@ -299,6 +302,79 @@ def ragged_leg(B, wl, torch, log, count=256, budget=150e9, launches=2, mode=None
                        "autotuned": sh["tuned"]} for sh in rb.shapes]}
 
 
+# Table 1 of the paper (RMS error of u_Gamma, n = 2^16 neurons in all): He,
+# manual and suggested initialisation at N = 2x2, 4x4, 8x8.
+PAPER_TABLE_1 = {"he": [8.4230e-03, 1.7173e-04, 1.1454e-05], "manual": [4.9389e-10, 4.0850e-09, 6.5790e-08],
+                 "suggested": [2.8926e-10, 7.5946e-10, 2.9894e-09]}
+
+
+def init_leg(B, wl, torch, log, seed=6000, grids=(2, 4, 8), neurons=400, q=40):
+    """Table-1-style comparison at the configs' scale, on the GPU: RMS error
+    of u_Gamma against the exact solution sin(2 pi x) e^y of the Section
+    5.2.1 Poisson problem for the He, manual and suggested (eq. init, with
+    the paper's c = 1/8 and with c = 1/4, the paper leaving c to be fixed on
+    small problems) hidden layers and for the configs' own U[-4, 4] draw in
+    local coordinates; five CholeskyQR passes;
+    N = 2x2, 4x4, 8x8 subdomains of `neurons` neurons and a q x q interior
+    grid (q points per edge) each, FP64, one timed solve per entry.  The
+    paper's own Table 1 (2^16 neurons in all, about one point per neuron) is
+    quoted beside it: at that point density the local feature matrices are
+    numerically singular for a full-rank least-squares solver."""
+    import dataclasses
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+    rows = []
+    for nx in grids:
+        P = wl.Problem(nx, nx, neurons, q, q, q, q, R=4.0, sol=wl.SOL_SIN2PI_EXP)
+        cp = B.make_problem(P.x0, P.x1, P.y0, P.y1, P.nsub_x, P.nsub_y, P.neurons, P.q_x, P.q_y,
+                            P.m_bdry_edge, P.m_ifc_edge, P.op)
+        plan = B.Plan(cp)
+        plan.set_kernels(-4, -1)
+        plan.set_passes(5)      # kappa(K_s) reaches 1e12-1e17 across these layers
+        s = plan.sizes
+        f, g, coef = wl.sample_data(P, plan.points(B.POINTS_INTERIOR), plan.points(B.POINTS_BOUNDARY))
+        gp = plan.points(B.POINTS_INTERFACE)
+        ue = wl.exact_u(P, gp[:, 0], gp[:, 1])
+        ex, ey = wl.eval_grid(P, 8)
+        uex = wl.exact_u(P, ex, ey)
+        dxy = t(np.stack([ex, ey], 1))
+        uh = torch.zeros(len(ex), dtype=torch.float64, device=dev)
+        df, dg = t(f), t(g)
+        du = torch.zeros(s.n_interface, dtype=torch.float64, device=dev)
+        dc = torch.zeros(s.nsub * s.neurons, dtype=torch.float64, device=dev)
+        for scheme, c in ((wl.INIT_HE, None), (wl.INIT_MANUAL, None), (wl.INIT_SUGGESTED, 0.125),
+                          (wl.INIT_SUGGESTED, 0.25), ("uniform_R4_local", None)):
+            if scheme == "uniform_R4_local":
+                W, b = wl.hidden_params(P, seed)
+                l = None
+            else:
+                W, b = wl.hidden_params_init(P, seed, scheme, c=c or 0.125)
+                l = wl.init_half_width(P, scheme, c or 0.125)
+            dW, db = t(W), t(b)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.solve(dW, db, df, dg, None, du, dc)
+            info = plan.solve_info()
+            el = time.perf_counter() - t0
+            ok = info.status == 0
+            if ok:
+                plan.eval(dW, db, dc, dxy, uh)
+            u = du.cpu().numpy()
+            rows.append({"N": "%dx%d" % (nx, nx), "init": scheme, "c": c, "l": l, "status": int(info.status),
+                         "bad_pass": int(info.bad_pass),
+                         "rms_u_gamma_vs_exact": float(np.sqrt(np.mean((u - ue) ** 2))) if ok else None,
+                         "rel_l2_uh_vs_exact": float(np.linalg.norm(uh.cpu().numpy() - uex) / np.linalg.norm(uex)) if ok else None,
+                         "seconds": el})
+            log("init leg: %dx%d %s c=%s status %d" % (nx, nx, scheme, c, info.status))
+        del plan, df, dg, du, dc, uh
+        torch.cuda.empty_cache()
+    return {"workload": "-Lap u = f, u = sin(2 pi x) e^y (Section 5.2.1) on [0,1]^2; %d tanh neurons and %dx%d "
+                        "interior points per subdomain, %d per edge; FP64" % (neurons, q, q, q),
+            "metric": "RMS error of u_Gamma at the interface points against the exact solution (as Table 1)",
+            "rows": rows,
+            "paper_table_1": {"neurons_in_all": 65536, "N": ["2x2", "4x4", "8x8"], **PAPER_TABLE_1}}
+
+
 def large_leg(B, wl, torch, log, cg_tol=1e-11):
     """The 32x32 variable-coefficient case (1024 subdomains, 1000 neurons,
     64x64 points, 126976 interface unknowns): matrix-free interface CG (a
@@ -353,6 +429,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the 16x16 learned warm-start leg")
     ap.add_argument("--no-ragged", action="store_true", help="skip the ragged-batch leg")
     ap.add_argument("--no-large", action="store_true", help="skip the 32x32 leg")
+    ap.add_argument("--no-init", action="store_true", help="skip the initialisation study (Table 1 style)")
     ap.add_argument("--batch", type=int, default=8, help="problem instances solved together per step")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration) and exit")
@@ -526,6 +603,10 @@ def main():
     if not args.no_ragged:
         ragged_out = ragged_leg(B, wl, torch, log)
         torch.cuda.empty_cache()
+    init_out = None
+    if not args.no_init:
+        init_out = init_leg(B, wl, torch, log)
+        torch.cuda.empty_cache()
     large_out = None
     if not args.no_large:
         large_out = large_leg(B, wl, torch, log)
@@ -557,6 +638,7 @@ def main():
         "learned": learned_out,
         "ragged": ragged_out,
         "large": large_out,
+        "init_study": init_out,
     }
     print(json.dumps(out), flush=True)
 

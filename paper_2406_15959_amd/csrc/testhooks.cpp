@@ -113,8 +113,7 @@ int elmddm_test_potrf(double* A, int lda, long long sA, int Mrows, int n, double
 // instruction can reach on this device, next to the published peak.
 // SHAPE 0: V_MFMA_F64_16X16X4, 8 independent accumulators per wave.
 // SHAPE 1: V_MFMA_F64_4X4X4_4B, a 4 x 4 outer product of operand registers
-// (16 accumulators per wave).  Operands change every iteration so that the
-// loop cannot be folded.
+// (16 accumulators per wave).
 template <int SHAPE>
 __global__ __launch_bounds__(256) void mfma_rate_kernel(double* out, int iters)
 {
@@ -122,12 +121,10 @@ __global__ __launch_bounds__(256) void mfma_rate_kernel(double* out, int iters)
     if (SHAPE == 0) {
         v4d acc[8];
         for (int j = 0; j < 8; ++j) acc[j] = (v4d){0.0, 0.0, 0.0, 0.0};
-        double a = threadIdx.x * 1e-3, b = 1.0 + blockIdx.x * 1e-6;
-        for (int i = 0; i < iters; ++i) {
+        const double a = threadIdx.x * 1e-3, b = 1.0 + blockIdx.x * 1e-6;
+        for (int i = 0; i < iters; ++i)
 #pragma unroll
             for (int j = 0; j < 8; ++j) acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[j], 0, 0, 0);
-            a = __shfl_xor(a, 1);
-        }
         for (int j = 0; j < 8; ++j) s += acc[j][0] + acc[j][1] + acc[j][2] + acc[j][3];
     } else {
         double acc[16], a[4], b[4];
@@ -136,15 +133,12 @@ __global__ __launch_bounds__(256) void mfma_rate_kernel(double* out, int iters)
             a[j] = threadIdx.x * 1e-3 + j;
             b[j] = 1.0 + blockIdx.x * 1e-6 + j;
         }
-        for (int i = 0; i < iters; ++i) {
+        for (int i = 0; i < iters; ++i)
 #pragma unroll
             for (int p = 0; p < 4; ++p)
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
                     acc[4 * p + q] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[p], b[q], acc[4 * p + q], 0, 0, 0);
-#pragma unroll
-            for (int p = 0; p < 4; ++p) a[p] = __shfl_xor(a[p], 1);
-        }
         for (int j = 0; j < 16; ++j) s += acc[j];
     }
     out[(size_t)blockIdx.x * blockDim.x + threadIdx.x] = s;

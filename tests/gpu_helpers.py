@@ -11,8 +11,9 @@ def to_c_problem(P):
                           P.m_bdry_edge, P.m_ifc_edge, P.op)
 
 
-def gpu_solve(P, seed, plan=None, keep_schur=False, eval_per_sub=16):
-    """Solve on the GPU through the C ABI.  Returns a dict of numpy arrays."""
+def gpu_solve(P, seed, plan=None, keep_schur=False, eval_per_sub=16, params=None):
+    """Solve on the GPU through the C ABI.  Returns a dict of numpy arrays.
+    params: (W, b) of the hidden layer, else drawn with hidden_params(P, seed)."""
     import torch
     from paper_2406_15959_amd import binding as B
     dev = torch.device("cuda:0")
@@ -20,7 +21,7 @@ def gpu_solve(P, seed, plan=None, keep_schur=False, eval_per_sub=16):
     if keep_schur:
         plan.keep_schur(True)
     s = plan.sizes
-    W, b = wl.hidden_params(P, seed)
+    W, b = params if params is not None else wl.hidden_params(P, seed)
     ipts = plan.points(B.POINTS_INTERIOR)
     bpts = plan.points(B.POINTS_BOUNDARY)
     f, g, coef = wl.sample_data(P, ipts, bpts)
@@ -48,11 +49,11 @@ def gpu_solve(P, seed, plan=None, keep_schur=False, eval_per_sub=16):
     return out
 
 
-def oracle_solve(P, seed, eval_per_sub=16):
+def oracle_solve(P, seed, eval_per_sub=16, params=None):
     from oracle import ddm
     from oracle.layout import build_layout
     lay = build_layout(P)
-    W, b = wl.hidden_params(P, seed)
+    W, b = params if params is not None else wl.hidden_params(P, seed)
     data = ddm.problem_data(P, lay, wl.source_f, wl.boundary_g, wl.coefficient)
     sol = ddm.solve(P, W, b, data, lay)
     ex, ey = wl.eval_grid(P, eval_per_sub)

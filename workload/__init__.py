@@ -23,6 +23,12 @@ import numpy as np
 OP_POISSON = 0
 OP_VARCOEF = 1
 
+# Manufactured solutions: u* = sin(pi x) sin(pi y) (zero on the boundary of
+# the unit square), or u* = sin(2 pi x) e^y, the exact solution of the 2-D
+# Poisson experiment of Section 5.2.1 (nonzero Dirichlet data on y = 0, 1).
+SOL_SINSIN = 0
+SOL_SIN2PI_EXP = 1
+
 
 @dataclasses.dataclass(frozen=True)
 class Problem:
@@ -35,6 +41,7 @@ class Problem:
     op           -- OP_POISSON or OP_VARCOEF
     R            -- hidden weights and biases are i.i.d. U[-R, R]
     k1, k2       -- wave numbers of the variable coefficient a(x, y)
+    sol          -- manufactured solution (SOL_SINSIN or SOL_SIN2PI_EXP)
     """
 
     nsub_x: int
@@ -52,6 +59,7 @@ class Problem:
     x1: float = 1.0
     y0: float = 0.0
     y1: float = 1.0
+    sol: int = SOL_SINSIN
 
     @property
     def nsub(self) -> int:
@@ -98,11 +106,105 @@ def hidden_params(problem: Problem, seed: int):
 
 
 # ---------------------------------------------------------------------------
-# Manufactured solution u* = sin(pi x) sin(pi y) and its data.
+# The paper's initialisation of the hidden layer (Section 4.1, eq. init) and
+# the two it is compared with (Table 1).  The half-width l = c sqrt(n)
+# (n = all neurons of the problem) comes from l ~ sqrt(n_N) for a subdomain
+# scaled to unit size, times the factor sqrt(N) that undoes the scaling, so
+# w and b = -w . xi act on the problem's own coordinates; xi is uniform on
+# the closed r-neighbourhood of the subdomain, r = diam(Omega_s) / 2.  The
+# local networks see x^ = 2 (x - x_c) / h in [-1, 1]^2, so a global draw
+# (w, b) maps exactly to w^ = w * h / 2, b^ = b + w . x_c.
 # ---------------------------------------------------------------------------
 
+def _dist_to_rect(px, py, wx, wy):
+    """Distance of points to the rectangle [0, wx] x [0, wy]."""
+    dx = np.maximum(np.maximum(-px, px - wx), 0.0)
+    dy = np.maximum(np.maximum(-py, py - wy), 0.0)
+    return np.hypot(dx, dy)
+
+
+def sample_rect_neighbourhood(rng, count: int, wx: float, wy: float, r: float):
+    """count points uniform on the closed r-neighbourhood of [0, wx] x [0, wy]
+    (the points at distance <= r from it), by rejection from its bounding
+    box.  Returns an array (count, 2)."""
+    out = np.empty((0, 2))
+    while len(out) < count:
+        need = count - len(out)
+        m = need + need // 4 + 16
+        cand = np.stack([rng.uniform(-r, wx + r, m), rng.uniform(-r, wy + r, m)], 1)
+        keep = cand[_dist_to_rect(cand[:, 0], cand[:, 1], wx, wy) <= r]
+        out = np.concatenate([out, keep])
+    return out[:count]
+
+
+INIT_SUGGESTED = "suggested"   # l = c sqrt(n), n = all neurons of the problem (eq. init), c = 1/8
+INIT_MANUAL = "manual"         # l = 1
+INIT_HE = "he"                 # l = sqrt(2 / n_N), n_N = neurons per subdomain
+
+
+def init_half_width(problem: Problem, scheme: str, c: float = 0.125) -> float:
+    """Half-width l of the weight interval [-l, l] of each scheme in Table 1
+    (problem coordinates)."""
+    if scheme == INIT_SUGGESTED:
+        return c * math.sqrt(problem.nsub * problem.neurons)
+    if scheme == INIT_MANUAL:
+        return 1.0
+    if scheme == INIT_HE:
+        return math.sqrt(2.0 / problem.neurons)
+    raise ValueError(scheme)
+
+
+def hidden_params_init(problem: Problem, seed: int, scheme: str = INIT_SUGGESTED, c: float = 0.125,
+                       return_global: bool = False):
+    """Hidden layer drawn as in eq. init: per subdomain and neuron, w ~
+    U([-l, l]^2) and b = -w . xi with xi uniform on the closed
+    r-neighbourhood of the subdomain, r = diam / 2, all in problem
+    coordinates.  The scheme sets l (init_half_width); the bias rule is the
+    same for all three.  Returns W (nsub, n, 2), b (nsub, n) for the local
+    networks' [-1, 1]^2 coordinates; with return_global also (w, b, xi) in
+    problem coordinates."""
+    rng = np.random.default_rng(seed)
+    N, n = problem.nsub, problem.neurons
+    hx = (problem.x1 - problem.x0) / problem.nsub_x
+    hy = (problem.y1 - problem.y0) / problem.nsub_y
+    r = 0.5 * math.hypot(hx, hy)
+    l = init_half_width(problem, scheme, c)
+    wg = rng.uniform(-l, l, size=(N, n, 2))
+    xi = sample_rect_neighbourhood(rng, N * n, hx, hy, r).reshape(N, n, 2)
+    s = np.arange(N)
+    lo = np.stack([problem.x0 + (s % problem.nsub_x) * hx, problem.y0 + (s // problem.nsub_x) * hy], 1)
+    xi = xi + lo[:, None, :]
+    bg = -(wg * xi).sum(-1)
+    ctr = lo + 0.5 * np.array([hx, hy])
+    W = wg * (0.5 * np.array([hx, hy]))
+    b = bg + (wg * ctr[:, None, :]).sum(-1)
+    W, b = np.ascontiguousarray(W), np.ascontiguousarray(b)
+    if return_global:
+        return W, b, (wg, bg, xi)
+    return W, b
+
+
+# ---------------------------------------------------------------------------
+# Manufactured solutions and their data.
+# ---------------------------------------------------------------------------
+
+def _u_and_grad(problem: Problem, x, y):
+    """u*, du*/dx, du*/dy and -Lap u* of the problem's manufactured solution."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    p = math.pi
+    if problem.sol == SOL_SIN2PI_EXP:
+        s, c, e = np.sin(2 * p * x), np.cos(2 * p * x), np.exp(y)
+        u = s * e
+        return u, 2 * p * c * e, u, (4 * p * p - 1.0) * u
+    u = np.sin(p * x) * np.sin(p * y)
+    ux = p * np.cos(p * x) * np.sin(p * y)
+    uy = p * np.sin(p * x) * np.cos(p * y)
+    return u, ux, uy, 2.0 * p * p * u
+
+
 def exact_u(problem: Problem, x, y):
-    return np.sin(math.pi * x) * np.sin(math.pi * y)
+    return _u_and_grad(problem, x, y)[0]
 
 
 def coefficient(problem: Problem, x, y):
@@ -121,21 +223,17 @@ def coefficient(problem: Problem, x, y):
 
 
 def source_f(problem: Problem, x, y):
-    """f = L u* for u* = sin(pi x) sin(pi y).
+    """f = L u* for the manufactured solution u*.
 
-    Poisson: f = 2 pi^2 u*.  Variable coefficient:
-    f = -a Lap u* - grad a . grad u* (product rule).
+    Poisson: f = -Lap u* (2 pi^2 u* for sin sin, (4 pi^2 - 1) u* for
+    sin(2 pi x) e^y).  Variable coefficient: f = -a Lap u* - grad a . grad u*
+    (product rule).
     """
-    x = np.asarray(x, dtype=np.float64)
-    y = np.asarray(y, dtype=np.float64)
-    p = math.pi
-    u = np.sin(p * x) * np.sin(p * y)
+    u, ux, uy, mlap = _u_and_grad(problem, x, y)
     if problem.op == OP_POISSON:
-        return 2.0 * p * p * u
+        return mlap
     a, ax, ay = coefficient(problem, x, y)
-    ux = p * np.cos(p * x) * np.sin(p * y)
-    uy = p * np.sin(p * x) * np.cos(p * y)
-    return a * (2.0 * p * p * u) - (ax * ux + ay * uy)
+    return a * mlap - (ax * ux + ay * uy)
 
 
 def boundary_g(problem: Problem, x, y):
