@@ -11,9 +11,10 @@ def to_c_problem(P):
                           P.m_bdry_edge, P.m_ifc_edge, P.op)
 
 
-def gpu_solve(P, seed, plan=None, keep_schur=False, eval_per_sub=16, params=None):
+def gpu_solve(P, seed, plan=None, keep_schur=False, eval_per_sub=16, params=None, data_fn=None):
     """Solve on the GPU through the C ABI.  Returns a dict of numpy arrays.
-    params: (W, b) of the hidden layer, else drawn with hidden_params(P, seed)."""
+    params: (W, b) of the hidden layer, else drawn with hidden_params(P, seed);
+    data_fn(P, interior_xy, boundary_xy) -> (f, g, coef), else sample_data."""
     import torch
     from paper_2406_15959_amd import binding as B
     dev = torch.device("cuda:0")
@@ -24,7 +25,7 @@ def gpu_solve(P, seed, plan=None, keep_schur=False, eval_per_sub=16, params=None
     W, b = params if params is not None else wl.hidden_params(P, seed)
     ipts = plan.points(B.POINTS_INTERIOR)
     bpts = plan.points(B.POINTS_BOUNDARY)
-    f, g, coef = wl.sample_data(P, ipts, bpts)
+    f, g, coef = (data_fn or wl.sample_data)(P, ipts, bpts)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
     dW, db, df = t(W), t(b), t(f)
     dg = t(g) if len(g) else None
@@ -49,12 +50,14 @@ def gpu_solve(P, seed, plan=None, keep_schur=False, eval_per_sub=16, params=None
     return out
 
 
-def oracle_solve(P, seed, eval_per_sub=16, params=None):
+def oracle_solve(P, seed, eval_per_sub=16, params=None, fns=None):
+    """fns: (source_f, boundary_g, coefficient) functions of (P, x, y), else
+    the manufactured solution's."""
     from oracle import ddm
     from oracle.layout import build_layout
     lay = build_layout(P)
     W, b = params if params is not None else wl.hidden_params(P, seed)
-    data = ddm.problem_data(P, lay, wl.source_f, wl.boundary_g, wl.coefficient)
+    data = ddm.problem_data(P, lay, *(fns or (wl.source_f, wl.boundary_g, wl.coefficient)))
     sol = ddm.solve(P, W, b, data, lay)
     ex, ey = wl.eval_grid(P, eval_per_sub)
     uh = ddm.evaluate(P, lay, W, b, sol.c, ex, ey)

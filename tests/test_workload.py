@@ -147,3 +147,48 @@ def test_he_and_manual_init_use_the_same_bias_rule():
         l = wl.init_half_width(P, scheme)
         assert np.abs(wg).max() <= l and np.abs(wg).max() > 0.9 * l
         assert np.allclose(bg, -(wg * xi).sum(-1), rtol=0, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# Approximate Gaussian random fields (eq. grf) and rho = tanh(grf) + 1.1
+# ---------------------------------------------------------------------------
+
+def test_grf_moments_match_the_distribution():
+    """E[grf^2] = terms * E[a^2] * E[sin^2] = alpha^4 / 2 (b uniform), and
+    E[|w|^2] = 2 alpha^2: checked over many independent fields."""
+    alpha = 16.0
+    x = np.array([0.3, 0.7])
+    y = np.array([0.2, 0.9])
+    vals, w2 = [], []
+    for seed in range(400):
+        F = wl.grf_params(seed, alpha)
+        vals.append(wl.grf_value_and_grad(F, x, y)[0])
+        w2.append(np.mean(np.sum(F.freq ** 2, 1)))
+    v = np.concatenate(vals)
+    assert abs(np.mean(v ** 2) / (alpha ** 4 / 2) - 1) < 0.1
+    assert abs(np.mean(w2) / (2 * alpha ** 2) - 1) < 0.02
+    F = wl.grf_params(1, alpha)
+    assert F.amp.shape == (256,) and F.freq.shape == (256, 2) and np.all((F.phase > 0) & (F.phase < 2 * math.pi))
+
+
+def test_grf_gradient_and_coefficient_by_finite_differences():
+    F = wl.grf_params(5, 16.0)
+    rng = np.random.default_rng(9)
+    x, y = rng.uniform(0, 1, 25), rng.uniform(0, 1, 25)
+    h = 1e-6
+    v, vx, vy = wl.grf_value_and_grad(F, x, y)
+    fd_x = (wl.grf_value_and_grad(F, x + h, y)[0] - wl.grf_value_and_grad(F, x - h, y)[0]) / (2 * h)
+    fd_y = (wl.grf_value_and_grad(F, x, y + h)[0] - wl.grf_value_and_grad(F, x, y - h)[0]) / (2 * h)
+    scale = np.abs(np.concatenate([vx, vy])).max()
+    assert np.abs(vx - fd_x).max() <= 1e-6 * scale and np.abs(vy - fd_y).max() <= 1e-6 * scale
+    a, ax, ay = wl.grf_coefficient(F, x, y)
+    assert np.all((a > 0.1 - 1e-15) & (a < 2.1 + 1e-15))
+    fa_x = (wl.grf_coefficient(F, x + h, y)[0] - wl.grf_coefficient(F, x - h, y)[0]) / (2 * h)
+    assert np.abs(ax - fa_x).max() <= 1e-5 * max(1.0, np.abs(ax).max())
+    # the data helpers: f = grf, g = 0 / f = 1, g = 0, coefficient rows like sample_data
+    P = dataclasses.replace(wl.CONFIG_SMALL, op=wl.OP_VARCOEF)
+    ip, bp = np.stack([x, y], 1), np.stack([y, x], 1)[:4]
+    f, g, c = wl.grf_source_data(P, F, ip, bp)
+    assert np.array_equal(f, v) and not g.any() and c is None
+    f, g, c = wl.grf_coefficient_data(P, F, ip, bp)
+    assert np.all(f == 1) and not g.any() and c.shape == (3, 25) and np.array_equal(c[0], a)

@@ -185,6 +185,60 @@ def hidden_params_init(problem: Problem, seed: int, scheme: str = INIT_SUGGESTED
 
 
 # ---------------------------------------------------------------------------
+# Approximate Gaussian random fields (Section 5.2.1, eq. grf): a sum of 256
+# random plane waves, used as a source f with g = 0, or through
+# rho = tanh(grf) + 1.1 as the coefficient of -div(rho grad u) = 1, g = 0
+# (Section 5.2.2).  Neither problem has a closed-form solution.
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass(frozen=True)
+class GRF:
+    amp: np.ndarray     # (terms,)  a_i ~ N(0, alpha^4 / terms)
+    freq: np.ndarray    # (terms, 2) w_i ~ N(0, alpha^2 I)
+    phase: np.ndarray   # (terms,)  b_i ~ U(0, 2 pi)
+
+
+def grf_params(seed: int, alpha: float, terms: int = 256) -> GRF:
+    rng = np.random.default_rng(seed)
+    amp = rng.normal(0.0, alpha * alpha / math.sqrt(terms), size=terms)
+    freq = rng.normal(0.0, alpha, size=(terms, 2))
+    phase = rng.uniform(0.0, 2.0 * math.pi, size=terms)
+    return GRF(amp, freq, phase)
+
+
+def grf_value_and_grad(field: GRF, x, y):
+    """grf(x, y) = sum_i a_i sin(w_i . x + b_i) and its gradient."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    arg = np.multiply.outer(x, field.freq[:, 0]) + np.multiply.outer(y, field.freq[:, 1]) + field.phase
+    v = np.sin(arg) @ field.amp
+    c = np.cos(arg) * field.amp
+    return v, c @ field.freq[:, 0], c @ field.freq[:, 1]
+
+
+def grf_source_data(problem: Problem, field: GRF, interior_xy, boundary_xy):
+    """f = grf at the interior points, g = 0 (Poisson with the field as source)."""
+    f = grf_value_and_grad(field, interior_xy[:, 0], interior_xy[:, 1])[0]
+    return f, np.zeros(len(boundary_xy)), None
+
+
+def grf_coefficient(field: GRF, x, y):
+    """rho = tanh(grf) + 1.1 and its gradient (1 - tanh^2) grad grf."""
+    v, vx, vy = grf_value_and_grad(field, x, y)
+    t = np.tanh(v)
+    d = 1.0 - t * t
+    return t + 1.1, d * vx, d * vy
+
+
+def grf_coefficient_data(problem: Problem, field: GRF, interior_xy, boundary_xy):
+    """-div(rho grad u) = 1, g = 0: f = 1, and (rho, rho_x, rho_y) at the
+    interior points stacked as (3, npts) like sample_data (problem.op must be
+    OP_VARCOEF)."""
+    a, ax, ay = grf_coefficient(field, interior_xy[:, 0], interior_xy[:, 1])
+    return np.ones(len(interior_xy)), np.zeros(len(boundary_xy)), np.stack([a, ax, ay])
+
+
+# ---------------------------------------------------------------------------
 # Manufactured solutions and their data.
 # ---------------------------------------------------------------------------
 
