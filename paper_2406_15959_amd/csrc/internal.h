@@ -167,9 +167,14 @@ void blocked_potrf(hipStream_t st, double* A, int lda, long long sA, int Mrows, 
 // overwritten by L^{-1} rhs (forward substitution fused with the panels).
 // The strictly lower 64 x 64 tiles of L are written to Lo (ld ldo); the
 // diagonal tiles stay in A and their inverses in Dinv.
+// With a side stream and two events (unfused path only), each step updates
+// just the next block column on st and runs the rest of its trailing update
+// on st2, overlapped with the next diagonal factorisation and panel
+// (lookahead); st waits for st2 before it returns.
 void envelope_potrf(hipStream_t st, double* A, int lda, long long sA, double* Lo, int ldo,
                     long long sLo, int n, const int* rend, double* Dinv, long long sD, DevInfo* info,
-                    int pass, double* dsave, double* rhs, long long sR, int batch, bool fused);
+                    int pass, double* dsave, double* rhs, long long sR, int batch, bool fused,
+                    hipStream_t st2 = nullptr, hipEvent_t ev_fork = nullptr, hipEvent_t ev_join = nullptr);
 
 void init_info(hipStream_t st, DevInfo* info);
 void check_finite(hipStream_t st, const double* v, long long count, DevInfo* info);

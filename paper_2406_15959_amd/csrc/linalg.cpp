@@ -44,29 +44,59 @@ void blocked_potrf(hipStream_t st, double* A, int lda, long long sA, int Mrows, 
 
 void envelope_potrf(hipStream_t st, double* A, int lda, long long sA, double* Lo, int ldo,
                     long long sLo, int n, const int* rend, double* Dinv, long long sD, DevInfo* info,
-                    int pass, double* dsave, double* rhs, long long sR, int batch, bool fused)
+                    int pass, double* dsave, double* rhs, long long sR, int batch, bool fused,
+                    hipStream_t st2, hipEvent_t ev_fork, hipEvent_t ev_join)
 {
     const double tau = 64.0 * n * 0x1p-53;
+    const bool look = !fused && st2 && ev_fork && ev_join;
+    bool pending = false;   // a trailing update of the previous step is running on st2
     if (dsave) save_diag(st, A, lda, sA, n, dsave, n, batch);
     for (int j = 0, p = 0; j < n; j += NB, ++p) {
         const int jb = std::min(NB, n - j);
         double* Dj = Dinv + (long long)p * NB * NB;
         const int r1 = std::min(n, rend[p]);
+        // Block column p is final here: the previous step updated it on st,
+        // and every earlier side-stream update was joined before that.
         potrf_diag(st, A, lda, sA, j, jb, Dj, sD, nullptr, 0, 0, info, pass, batch, dsave, n, tau, rhs,
                    sR);
         if (fused) {
             // one launch: latency-optimal for a few matrices (panel tiles recomputed per pair)
             envelope_step(st, A, lda, sA, Lo, ldo, sLo, j, jb, Dj, sD, r1, rhs, sR, batch);
-        } else {
-            // panel, then one trailing GEMM: throughput-optimal for many matrices
-            envelope_panel(st, A, lda, sA, Lo, ldo, sLo, j, jb, Dj, sD, r1, rhs, sR, batch);
-            const int Mb = r1 - j - jb;
+            continue;
+        }
+        // panel, then the trailing GEMM: throughput-optimal for many matrices
+        envelope_panel(st, A, lda, sA, Lo, ldo, sLo, j, jb, Dj, sD, r1, rhs, sR, batch);
+        const int Mb = r1 - j - jb;
+        const double* Lp = Lo + (long long)j * ldo + j + jb;
+        double* Tr = A + (long long)(j + jb) * lda + (j + jb);
+        if (!look) {
             if (Mb > 0)
-                gemm_f64(st, false, true, 0, true, Mb, Mb, jb, -1.0, Lo + (long long)j * ldo + j + jb, ldo,
-                         sLo, Lo + (long long)j * ldo + j + jb, ldo, sLo, 1.0,
-                         A + (long long)(j + jb) * lda + (j + jb), lda, sA, batch);
+                gemm_f64(st, false, true, 0, true, Mb, Mb, jb, -1.0, Lp, ldo, sLo, Lp, ldo, sLo, 1.0, Tr, lda, sA,
+                         batch);
+            continue;
+        }
+        // The previous step's side-stream update also wrote the next block
+        // column: wait for it before touching that column.
+        if (pending) {
+            (void)hipStreamWaitEvent(st, ev_join, 0);
+            pending = false;
+        }
+        if (Mb <= 0) continue;
+        const int na = std::min(NB, Mb);
+        // next block column (all its rows), on st: the next step needs it first
+        gemm_f64(st, false, true, 0, false, Mb, na, jb, -1.0, Lp, ldo, sLo, Lp, ldo, sLo, 1.0, Tr, lda, sA, batch);
+        const int Mr = Mb - na;
+        if (Mr > 0) {
+            // the rest of the trailing matrix (lower part), on st2
+            (void)hipEventRecord(ev_fork, st);
+            (void)hipStreamWaitEvent(st2, ev_fork, 0);
+            gemm_f64(st2, false, true, 0, true, Mr, Mr, jb, -1.0, Lp + na, ldo, sLo, Lp + na, ldo, sLo, 1.0,
+                     Tr + (long long)na * lda + na, lda, sA, batch);
+            (void)hipEventRecord(ev_join, st2);
+            pending = true;
         }
     }
+    if (pending) (void)hipStreamWaitEvent(st, ev_join, 0);
 }
 
 }  // namespace elmddm

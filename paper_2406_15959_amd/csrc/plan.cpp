@@ -105,6 +105,9 @@ struct elmddm_plan {
     bool schur_valid = false;
     hipStream_t last_stream = nullptr;
     bool solved = false;
+    // side stream and fork / join events of the envelope Cholesky's lookahead
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // interface system without a dense S: CG on the matrix-free operator
     bool mfree = false;
     double cg_tol = 1e-12;
@@ -207,6 +210,12 @@ struct elmddm_plan {
             for (auto& e : ev) (void)hipEventDestroy(e);
             for (auto& e : pev) (void)hipEventDestroy(e);
         }
+        if (side) {
+            (void)hipStreamSynchronize(side);
+            (void)hipStreamDestroy(side);
+        }
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
         for (void* q : allocs) (void)hipFree(q);
     }
 };
@@ -670,6 +679,12 @@ elmddm_status elmddm_plan_create_ex(const elmddm_problem* problem, int32_t batch
     } catch (const std::bad_alloc&) {
         st = fail(ELMDDM_OOM, "host allocation failed while building the layout");
     }
+    if (st == ELMDDM_OK && !P->mfree && !P->env_fused && P->nG > 0) {
+        if (hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming) != hipSuccess)
+            st = check_launch("side stream");
+    }
     if (st != ELMDDM_OK) {
         delete P;
         return st;
@@ -1051,8 +1066,14 @@ elmddm_status elmddm_solve(elmddm_plan* P, const double* W, const double* b, con
             // forward substitution fused (yvec <- L^{-1} rhs), then L^T u = y
             // block by block, then back to the interface numbering.
             const long long sDS = (long long)P->nblkS * NB * NB;
+            // the lookahead's side stream is used only outside stream capture
+            // (captured solves keep the single-stream order)
+            hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+            if (hipStreamIsCapturing(st, &cap) != hipSuccess) cap = hipStreamCaptureStatusActive;
+            const bool look = cap == hipStreamCaptureStatusNone;
             envelope_potrf(st, P->Sx, P->lds, sS, P->SL, P->lds, sS, P->nG, P->rend.data(), P->DinvS, sDS,
-                           P->d_info, -1, P->dsave, P->yvec, P->nG, B, P->env_fused);
+                           P->d_info, -1, P->dsave, P->yvec, P->nG, B, P->env_fused, look ? P->side : nullptr,
+                           P->ev_fork, P->ev_join);
             P->mark(6, st);
             const int BR = 4 * NB;
             for (int j0 = (P->nG - 1) / BR * BR; j0 >= 0; j0 -= BR) {

@@ -50,6 +50,38 @@ def test_graph_replays_equal_eager_solves(gpu):
         torch.cuda.synchronize()
 
 
+
+def test_batched_plan_graph_replays_equal_eager_solves(gpu):
+    """A batch of 4 instances takes the unfused interface factorisation,
+    whose eager solves overlap the trailing updates on a side stream
+    (lookahead); a captured solve keeps one stream.  Both orders give the
+    same bits, replay after replay."""
+    import torch
+    from paper_2406_15959_amd import binding as B
+    P = wl.Problem(4, 3, 80, 12, 11, 10, 9, R=2.0)
+    nb = 4
+    plan = B.Plan(to_c_problem(P), batch=nb)
+    s = plan.sizes
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda:0")
+    Ws, bs = zip(*[wl.hidden_params(P, 60 + i) for i in range(nb)])
+    f, g, _ = wl.sample_data(P, plan.points(B.POINTS_INTERIOR), plan.points(B.POINTS_BOUNDARY))
+    a = dict(W=t(np.stack(Ws)), b=t(np.stack(bs)), f=t(np.stack([f] * nb)), g=t(np.stack([g] * nb)), coef=None,
+             u_gamma=torch.zeros(nb * s.n_interface, dtype=torch.float64, device="cuda:0"),
+             c=torch.zeros(nb * s.nsub * s.neurons, dtype=torch.float64, device="cuda:0"))
+    u_e, c_e = torch.zeros_like(a["u_gamma"]), torch.zeros_like(a["c"])
+    plan.solve(a["W"], a["b"], a["f"], a["g"], None, u_e, c_e)
+    assert plan.solve_info().status == 0
+    graph = B.Graph([(plan, a)])
+    for rep in range(3):
+        a["u_gamma"].zero_()
+        a["c"].zero_()
+        graph.launch()
+        assert graph.info(0).status == 0
+        assert torch.equal(a["u_gamma"], u_e) and torch.equal(a["c"], c_e), rep
+        plan.solve(a["W"], a["b"], a["f"], a["g"], None, torch.zeros_like(u_e), torch.zeros_like(c_e))
+        torch.cuda.synchronize()
+
+
 @pytest.mark.parametrize("mode,tol", [("fp64", 1e-8), ("mixed", 1e-6)])
 def test_ragged_batch_in_one_graph_matches_oracle(gpu, mode, tol):
     import torch
