@@ -1337,8 +1337,11 @@ __global__ __launch_bounds__(256) void schur_sblocks_kernel(int nE, int mg, cons
                                                             const int32_t* perm, int ngeo,
                                                             long long sM, long long sS)
 {
-    __shared__ double M1[64 * 64];
-    __shared__ double M2[64 * 64];
+    // M blocks staged column-major with a padded column stride (mg + 1
+    // doubles): the lanes of a wave read consecutive columns r at the same p,
+    // which a stride of mg (e.g. 40) would fold onto a few LDS banks
+    __shared__ double M1[64 * 65];
+    __shared__ double M2[64 * 65];
     const int E1 = blockIdx.x, E2 = blockIdx.y;
     {
         const long long inst = blockIdx.z;
@@ -1369,10 +1372,12 @@ __global__ __launch_bounds__(256) void schur_sblocks_kernel(int nE, int mg, cons
     for (int it = mptr[blk]; it < mptr[blk + 1]; ++it) {
         const double* A1 = Mbuf + (long long)mdesc[2 * it] * mm;
         const double* A2 = Mbuf + (long long)mdesc[2 * it + 1] * mm;
+        const int ms = mg + 1;
         __syncthreads();
         for (int idx = tid; idx < mm; idx += 256) {
-            M1[idx] = A1[idx];
-            M2[idx] = A2[idx];
+            const int q = (idx / mg) * ms + idx % mg;
+            M1[q] = A1[idx];
+            M2[q] = A2[idx];
         }
         __syncthreads();
 #pragma unroll
@@ -1381,7 +1386,7 @@ __global__ __launch_bounds__(256) void schur_sblocks_kernel(int nE, int mg, cons
             if (idx < mm) {
                 const int r = idx % mg, c = idx / mg;
                 double v = 0.0;
-                for (int p = 0; p < mg; ++p) v += M1[r * mg + p] * M2[c * mg + p];
+                for (int p = 0; p < mg; ++p) v += M1[r * ms + p] * M2[c * ms + p];
                 acc[t] += v;
             }
         }
