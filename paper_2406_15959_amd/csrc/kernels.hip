@@ -1163,14 +1163,14 @@ void envelope_panel(hipStream_t st, const double* A, int lda, long long sA, doub
 }
 
 // Backward substitution L^T u = y over one block row of up to 256 rows
-// [j0, j0 + br): every workgroup solves the block's four 64-row sub-blocks in
-// turn (using their diagonal inverses and the L tiles inside the block), then
-// updates y_K -= L_{block,K}^T u_block for its share of the columns
-// K in [kbeg, j0) (one wave per column, lanes along the rows).
-__global__ __launch_bounds__(256) void trsv_lt_block_kernel(const double* L, int ld, long long sL,
-                                                            int j0, int br, int kbeg,
-                                                            const double* Dinv, long long sD,
-                                                            double* y, double* u, long long sY)
+// [j0, j0 + br), in two launches.  trsv_lt_diag_kernel (one workgroup per
+// system) solves the block's four 64-row sub-blocks in turn, using their
+// diagonal inverses and the L tiles inside the block, and writes u_block;
+// trsv_lt_offdiag_kernel then updates y_K -= L_{block,K}^T u_block for the
+// columns K in [kbeg, j0) (one wave per column, lanes along the rows).
+__global__ __launch_bounds__(256) void trsv_lt_diag_kernel(const double* L, int ld, long long sL, int j0, int br,
+                                                           const double* Dinv, long long sD, const double* y,
+                                                           double* u, long long sY)
 {
     {
         const long long zb = blockIdx.y;
@@ -1181,6 +1181,7 @@ __global__ __launch_bounds__(256) void trsv_lt_block_kernel(const double* L, int
     }
     __shared__ double yb[256], ub[256];
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
     yb[tid] = tid < br ? y[j0 + tid] : 0.0;
     ub[tid] = 0.0;
     __syncthreads();
@@ -1190,25 +1191,43 @@ __global__ __launch_bounds__(256) void trsv_lt_block_kernel(const double* L, int
         // y_sb -= sum over later sub-blocks of L[later, sb]^T u_later: one wave
         // per column of the sub-block, lanes along the (contiguous) rows
         if (s0 + 64 < br) {
-            const int ln = tid & 63;
-            for (int t = tid >> 6; t < sl; t += 4) {
+            for (int t = wave; t < sl; t += 4) {
                 const double* colp = L + (long long)(j0 + s0 + t) * ld + j0;
                 double v = 0.0;
-                for (int r = s0 + 64 + ln; r < br; r += 64) v += colp[r] * ub[r];
+                for (int r = s0 + 64 + lane; r < br; r += 64) v += colp[r] * ub[r];
                 v = wave_sum(v);
-                if (ln == 0) yb[s0 + t] -= v;
+                if (lane == 0) yb[s0 + t] -= v;
             }
             __syncthreads();
         }
-        if (tid < sl) {
-            const double* D = Dinv + (long long)((j0 + s0) / 64) * 64 * 64;
-            double acc = 0.0;
-            for (int i = tid; i < sl; ++i) acc += D[tid * 64 + i] * yb[s0 + i];
-            ub[s0 + tid] = acc;
+        // u_sb = D y_sb with D the stored inverse factor of the diagonal
+        // sub-block (row t holds D[t][i] at t * 64 + i, i >= t): one wave per
+        // row, lanes along the row (coalesced)
+        const double* D = Dinv + (long long)((j0 + s0) / 64) * 64 * 64;
+        for (int t = wave; t < sl; t += 4) {
+            double v = (lane >= t && lane < sl) ? D[t * 64 + lane] * yb[s0 + lane] : 0.0;
+            v = wave_sum(v);
+            if (lane == 0) ub[s0 + t] = v;
         }
         __syncthreads();
     }
-    if (blockIdx.x == 0 && tid < br) u[j0 + tid] = ub[tid];
+    if (tid < br) u[j0 + tid] = ub[tid];
+}
+
+__global__ __launch_bounds__(256) void trsv_lt_offdiag_kernel(const double* L, int ld, long long sL, int j0,
+                                                              int br, int kbeg, double* y, const double* u,
+                                                              long long sY)
+{
+    {
+        const long long zb = blockIdx.y;
+        L += zb * sL;
+        y += zb * sY;
+        u += zb * sY;
+    }
+    __shared__ double ub[256];
+    const int tid = threadIdx.x;
+    ub[tid] = tid < br ? u[j0 + tid] : 0.0;
+    __syncthreads();
     const int lane = tid & 63;
     const int wave = blockIdx.x * 4 + (tid >> 6);
     const int nwave = gridDim.x * 4;
@@ -1225,10 +1244,13 @@ void trsv_lower_t_block(hipStream_t st, const double* L, int ld, long long sL, i
                         int kbeg, const double* Dinv, long long sD, double* y, double* u,
                         long long sY, int batch)
 {
+    hipLaunchKernelGGL(trsv_lt_diag_kernel, dim3(1, batch), dim3(256), 0, st, L, ld, sL, j0, br, Dinv, sD, y, u,
+                       sY);
+    if (j0 <= kbeg) return;
     int nb = (j0 - kbeg + 7) / 8;   // about two columns per wave
     nb = nb < 1 ? 1 : (nb > 1024 ? 1024 : nb);
-    hipLaunchKernelGGL(trsv_lt_block_kernel, dim3(nb, batch), dim3(256), 0, st, L, ld, sL, j0, br, kbeg,
-                       Dinv, sD, y, u, sY);
+    hipLaunchKernelGGL(trsv_lt_offdiag_kernel, dim3(nb, batch), dim3(256), 0, st, L, ld, sL, j0, br, kbeg, y, u,
+                       sY);
 }
 
 __global__ void save_diag_kernel(const double* A, int lda, long long sA, int n, double* d,
