@@ -375,6 +375,71 @@ def init_leg(B, wl, torch, log, seed=6000, grids=(2, 4, 8), neurons=400, q=40):
             "paper_table_1": {"neurons_in_all": 65536, "N": ["2x2", "4x4", "8x8"], **PAPER_TABLE_1}}
 
 
+# Table 2 of the paper (u = sin(2 pi x) e^y, n = 2^16 neurons in all, CPU):
+# relative L2 and H1 errors and wall-clock seconds per N.
+PAPER_TABLE_2 = {"N": ["1x1", "2x2", "4x4", "8x8", "16x16"],
+                 "rel_l2": [8.1550e-11, 1.0748e-10, 1.6192e-08, 2.6392e-08, 1.0212e-07],
+                 "rel_h1": [1.6095e-09, 1.0590e-09, 3.2441e-08, 8.1948e-08, 1.5199e-07],
+                 "seconds": [8617.13, 315.83, 19.46, 3.48, 10.43]}
+
+
+def accuracy_leg(B, wl, torch, log, seed=6000, grids=(1, 2, 4, 8, 16), neurons=400, q=40, reps=3):
+    """Table-2-style accuracy on the GPU: relative L2 and H1 errors of u_h
+    against u = sin(2 pi x) e^y (Section 5.2.1) on 16 x 16 evaluation points
+    per subdomain, N = 1x1 (plain ELM) ... 16x16 subdomains of `neurons`
+    neurons and q x q interior points (q per edge), the paper's initialisation
+    (eq. init, c = 1/8), FP64 with five CholeskyQR passes; and the time of
+    one solve (median of `reps`, after a warm-up).  The paper's Table 2 (2^16
+    neurons in all, CPU) is quoted beside it."""
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+    rows = []
+    for nx in grids:
+        P = wl.Problem(nx, nx, neurons, q, q, q, q, sol=wl.SOL_SIN2PI_EXP)
+        cp = B.make_problem(P.x0, P.x1, P.y0, P.y1, P.nsub_x, P.nsub_y, P.neurons, P.q_x, P.q_y,
+                            P.m_bdry_edge, P.m_ifc_edge, P.op)
+        plan = B.Plan(cp)
+        plan.set_kernels(-4, -1)
+        plan.set_passes(5)
+        s = plan.sizes
+        f, g, _ = wl.sample_data(P, plan.points(B.POINTS_INTERIOR), plan.points(B.POINTS_BOUNDARY))
+        W, b = wl.hidden_params_init(P, seed, wl.INIT_SUGGESTED)
+        dW, db, df, dg = t(W), t(b), t(f), t(g) if len(g) else None
+        du = torch.zeros(max(s.n_interface, 1), dtype=torch.float64, device=dev)
+        dc = torch.zeros(s.nsub * s.neurons, dtype=torch.float64, device=dev)
+        uarg = du if s.n_interface else None
+        times = []
+        for it in range(reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.solve(dW, db, df, dg, None, uarg, dc)
+            info = plan.solve_info()
+            if it:
+                times.append(time.perf_counter() - t0)
+        ex, ey = wl.eval_grid(P, 16)
+        xy = t(np.stack([ex, ey], 1))
+        uh, ux, uy = (torch.zeros(len(ex), dtype=torch.float64, device=dev) for _ in range(3))
+        plan.eval_grad(dW, db, dc, xy, uh, ux, uy)
+        torch.cuda.synchronize()
+        ue = wl.exact_u(P, ex, ey)
+        gx, gy = wl.exact_grad(P, ex, ey)
+        uh, ux, uy = uh.cpu().numpy(), ux.cpu().numpy(), uy.cpu().numpy()
+        l2 = float(np.linalg.norm(uh - ue) / np.linalg.norm(ue))
+        h1 = float(np.sqrt((np.sum((uh - ue) ** 2) + np.sum((ux - gx) ** 2) + np.sum((uy - gy) ** 2))
+                           / (np.sum(ue ** 2) + np.sum(gx ** 2) + np.sum(gy ** 2))))
+        rows.append({"N": "%dx%d" % (nx, nx), "neurons_in_all": neurons * nx * nx, "status": int(info.status),
+                     "rel_l2": l2 if info.status == 0 else None, "rel_h1": h1 if info.status == 0 else None,
+                     "seconds_per_solve": float(np.median(times))})
+        log("accuracy leg: %dx%d status %d rel L2 %.2e H1 %.2e" % (nx, nx, info.status, l2, h1))
+        del plan, dW, db, df, dg, du, dc
+        torch.cuda.empty_cache()
+    return {"workload": "-Lap u = f, u = sin(2 pi x) e^y (Section 5.2.1) on [0,1]^2; %d tanh neurons and %dx%d "
+                        "interior points per subdomain, %d per edge; eq. init with c = 1/8; FP64, 5 CholeskyQR "
+                        "passes; one instance per solve" % (neurons, q, q, q),
+            "metric": "relative L2 and H1 (full norm) errors on 16x16 points per subdomain, as Table 2",
+            "rows": rows, "paper_table_2": PAPER_TABLE_2}
+
+
 def large_leg(B, wl, torch, log, cg_tol=1e-11):
     """The 32x32 variable-coefficient case (1024 subdomains, 1000 neurons,
     64x64 points, 126976 interface unknowns): matrix-free interface CG (a
@@ -429,7 +494,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the 16x16 learned warm-start leg")
     ap.add_argument("--no-ragged", action="store_true", help="skip the ragged-batch leg")
     ap.add_argument("--no-large", action="store_true", help="skip the 32x32 leg")
-    ap.add_argument("--no-init", action="store_true", help="skip the initialisation study (Table 1 style)")
+    ap.add_argument("--no-init", action="store_true",
+                    help="skip the initialisation study and the accuracy table (Tables 1 and 2 style)")
     ap.add_argument("--batch", type=int, default=8, help="problem instances solved together per step")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration) and exit")
@@ -603,9 +669,11 @@ def main():
     if not args.no_ragged:
         ragged_out = ragged_leg(B, wl, torch, log)
         torch.cuda.empty_cache()
-    init_out = None
+    init_out = acc_out = None
     if not args.no_init:
         init_out = init_leg(B, wl, torch, log)
+        torch.cuda.empty_cache()
+        acc_out = accuracy_leg(B, wl, torch, log)
         torch.cuda.empty_cache()
     large_out = None
     if not args.no_large:
@@ -639,6 +707,7 @@ def main():
         "ragged": ragged_out,
         "large": large_out,
         "init_study": init_out,
+        "accuracy_table": acc_out,
     }
     print(json.dumps(out), flush=True)
 

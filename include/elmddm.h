@@ -206,6 +206,15 @@ elmddm_status elmddm_solve_info(elmddm_plan* plan, elmddm_info* info);
 elmddm_status elmddm_eval(elmddm_plan* plan, const double* W, const double* b, const double* c,
                           const double* xy, int64_t npts, double* u, void* stream);
 
+/* u_h and its gradient at npts points (device arrays, same owner rule as
+ * elmddm_eval): writes u [npts] (if not NULL), dudx [npts] and dudy [npts],
+ * the derivatives of the owning local network (for the relative H1 errors
+ * reported in Section 5.2.1, Table 2).  INVALID_ARG on NULL W, b, c, or on
+ * NULL xy, dudx or dudy with npts > 0. */
+elmddm_status elmddm_eval_grad(elmddm_plan* plan, const double* W, const double* b, const double* c,
+                               const double* xy, int64_t npts, double* u, double* dudx, double* dudy,
+                               void* stream);
+
 /* The feature-assembly stage alone (the rows of eq. nonoverlap_discrete):
  * writes, per subdomain s, K^s in column-major [nsub][neurons][max_rows]
  * (rows: interior, boundary, interface; rows beyond m_s are zero), the flux

@@ -258,6 +258,23 @@ def evaluate(problem, layout, W, b, cs, x, y):
     return out
 
 
+def evaluate_grad(problem, layout, W, b, cs, x, y):
+    """u_h and its gradient (u_x, u_y) at arbitrary points, from the owning
+    subdomain's network: grad phi_j = sigma'(z_j) (w_j scaled by 2 / h)."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    own = owner_subdomain(problem, x, y)
+    u, ux, uy = np.zeros(len(x)), np.zeros(len(x)), np.zeros(len(x))
+    for s, sub in enumerate(layout.subs):
+        sel = np.nonzero(own == s)[0]
+        if len(sel) == 0:
+            continue
+        pts = np.stack([x[sel], y[sel]], axis=1)
+        phi, px, py, _ = features(W[s], b[s], sub.center, (sub.hx, sub.hy), pts)
+        u[sel], ux[sel], uy[sel] = phi @ cs[s], px @ cs[s], py @ cs[s]
+    return u, ux, uy
+
+
 def ddm_objective(layout, blocks, kps, u):
     """J(u) = ||(I - K K^+)(F - B u)||^2 + ||A K^+ (F - B u)||^2, the least-squares
     objective of eq. eliminated after minimising over c (eq. LS_system)."""

@@ -35,7 +35,7 @@ PLAN_DENSE = 2
 
 EXPORTED = [
     "elmddm_plan_create", "elmddm_plan_create_batch", "elmddm_plan_destroy", "elmddm_plan_sizes", "elmddm_points",
-    "elmddm_solve", "elmddm_solve_info", "elmddm_eval", "elmddm_assemble",
+    "elmddm_solve", "elmddm_solve_info", "elmddm_eval", "elmddm_eval_grad", "elmddm_assemble",
     "elmddm_plan_keep_schur", "elmddm_get_schur", "elmddm_set_timing", "elmddm_stage_times", "elmddm_pass_times",
     "elmddm_autotune", "elmddm_autotune_times", "elmddm_plan_set_kernels", "elmddm_plan_set_mode", "elmddm_plan_set_passes", "elmddm_plan_reserve_rhs", "elmddm_solve_rhs",
     "elmddm_schur_rhs", "elmddm_interface_cg",
@@ -102,6 +102,7 @@ def lib():
         L.elmddm_solve.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp, vp]
         L.elmddm_solve_info.argtypes = [vp, ctypes.POINTER(Info)]
         L.elmddm_eval.argtypes = [vp, dp, dp, dp, dp, i64, dp, vp]
+        L.elmddm_eval_grad.argtypes = [vp, dp, dp, dp, dp, i64, dp, dp, dp, vp]
         L.elmddm_assemble.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp, dp, vp]
         L.elmddm_plan_keep_schur.argtypes = [vp, i32]
         L.elmddm_get_schur.argtypes = [vp, dp, dp, vp]
@@ -227,6 +228,11 @@ class Plan:
     def eval(self, W, b, c, xy, u):
         _check(lib().elmddm_eval(self._h, _ptr(W), _ptr(b), _ptr(c), _ptr(xy), xy.shape[0], _ptr(u),
                                  _stream()))
+
+    def eval_grad(self, W, b, c, xy, u, dudx, dudy):
+        """u_h (u may be None) and its gradient at the points xy."""
+        _check(lib().elmddm_eval_grad(self._h, _ptr(W), _ptr(b), _ptr(c), _ptr(xy), xy.shape[0],
+                                      _ptr(u) if u is not None else None, _ptr(dudx), _ptr(dudy), _stream()))
 
     def assemble(self, W, b, f, g, coef, K, A, F):
         _check(lib().elmddm_assemble(self._h, _ptr(W), _ptr(b), _ptr(f), _ptr(g), _ptr(coef),

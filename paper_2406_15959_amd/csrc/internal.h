@@ -146,6 +146,9 @@ void local_backsolve(hipStream_t st, int N, int ngeo, long long nG, int n, int k
 void eval_points(hipStream_t st, int npts, const double* xy, int nx, int ny, double x0, double x1,
                  double y0, double y1, int n, const double* W, const double* b, const double* c,
                  double* u);
+void eval_points_grad(hipStream_t st, int npts, const double* xy, int nx, int ny, double x0, double x1,
+                      double y0, double y1, int n, const double* W, const double* b, const double* c,
+                      double* u, double* ux, double* uy);
 
 constexpr int NB = 64;  // block size of the blocked Cholesky
 

@@ -1615,6 +1615,50 @@ void eval_points(hipStream_t st, int npts, const double* xy, int nx, int ny, dou
                        x0, x1, y0, y1, n, W, b, c, u);
 }
 
+// u_h and its gradient: d/dx sum_j c_j tanh(z_j) = sum_j c_j (1 - t_j^2) w_j,x (2 / h_x),
+// likewise in y (the local networks see xhat = 2 (x - x_c) / h_x).  u may be NULL.
+__global__ void eval_grad_kernel(int npts, const double* xy, int nx, int ny, double x0, double x1, double y0,
+                                 double y1, int n, const double* W, const double* b, const double* c, double* u,
+                                 double* ux, double* uy)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npts) return;
+    const double x = xy[2 * p], y = xy[2 * p + 1];
+    const double hx = (x1 - x0) / nx, hy = (y1 - y0) / ny;
+    int sx = (int)floor((x - x0) * nx / (x1 - x0));
+    int sy = (int)floor((y - y0) * ny / (y1 - y0));
+    sx = sx < 0 ? 0 : (sx > nx - 1 ? nx - 1 : sx);
+    sy = sy < 0 ? 0 : (sy > ny - 1 ? ny - 1 : sy);
+    const int s = sy * nx + sx;
+    const double xc = (x0 + sx * hx) + 0.5 * hx;
+    const double yc = (y0 + sy * hy) + 0.5 * hy;
+    const double xh = (x - xc) * (2.0 / hx);
+    const double yh = (y - yc) * (2.0 / hy);
+    const double* Ws = W + (long long)s * n * 2;
+    const double* bs = b + (long long)s * n;
+    const double* cs = c + (long long)s * n;
+    double a0 = 0.0, ax = 0.0, ay = 0.0;
+    for (int j = 0; j < n; ++j) {
+        const double t = tanh(Ws[2 * j] * xh + Ws[2 * j + 1] * yh + bs[j]);
+        const double d = cs[j] * (1.0 - t * t);
+        a0 += cs[j] * t;
+        ax += d * Ws[2 * j];
+        ay += d * Ws[2 * j + 1];
+    }
+    if (u) u[p] = a0;
+    ux[p] = ax * (2.0 / hx);
+    uy[p] = ay * (2.0 / hy);
+}
+
+void eval_points_grad(hipStream_t st, int npts, const double* xy, int nx, int ny, double x0, double x1,
+                      double y0, double y1, int n, const double* W, const double* b, const double* c,
+                      double* u, double* ux, double* uy)
+{
+    if (npts <= 0) return;
+    hipLaunchKernelGGL(eval_grad_kernel, dim3((npts + 255) / 256), dim3(256), 0, st, npts, xy, nx, ny, x0, x1,
+                       y0, y1, n, W, b, c, u, ux, uy);
+}
+
 __global__ void init_info_kernel(DevInfo* info)
 {
     info->status = 0;

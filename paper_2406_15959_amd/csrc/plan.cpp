@@ -1404,6 +1404,16 @@ elmddm_status elmddm_eval(elmddm_plan* P, const double* W, const double* b, cons
     return check_launch("eval");
 }
 
+elmddm_status elmddm_eval_grad(elmddm_plan* P, const double* W, const double* b, const double* c,
+                               const double* xy, int64_t npts, double* u, double* dudx, double* dudy, void* stream)
+{
+    if (!P || !W || !b || !c || (npts > 0 && (!xy || !dudx || !dudy))) return fail(ELMDDM_INVALID_ARG, "NULL argument");
+    if (npts < 0 || npts > INT_MAX) return fail(ELMDDM_INVALID_ARG, "npts out of range");
+    eval_points_grad((hipStream_t)stream, (int)npts, xy, P->nx, P->ny, P->p.x0, P->p.x1, P->p.y0, P->p.y1, P->n, W,
+                     b, c, u, dudx, dudy);
+    return check_launch("eval_grad");
+}
+
 elmddm_status elmddm_set_timing(elmddm_plan* P, int32_t enable)
 {
     if (!P) return fail(ELMDDM_INVALID_ARG, "NULL plan");

@@ -274,3 +274,31 @@ def test_800_neuron_variable_coefficient_problem_matches_oracle(gpu, mode, tol):
     assert g["info"].status == 0, (g["info"].status, g["info"].bad_pass)
     assert rel(g["u_gamma"], o["u_gamma"]) <= tol
     assert rel(g["uh"], o["uh"]) <= tol
+
+
+def test_gradient_evaluation_matches_oracle(gpu):
+    """elmddm_eval_grad on the oracle's own coefficients (a kernel check,
+    1e-12) and the relative H1 seminorm error of a full GPU solve against the
+    oracle's (the H1 column of Table 2, 1e-8)."""
+    import dataclasses
+    import torch
+    from oracle import ddm
+    P = dataclasses.replace(wl.CONFIG_SMALL, sol=wl.SOL_SIN2PI_EXP)
+    g = gpu_solve(P, 7)
+    o = oracle_solve(P, 7)
+    lay = o["layout"]
+    ex, ey = wl.eval_grid(P, 8)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    xy = t(np.stack([ex, ey], 1))
+    W, b = t(g["W"]), t(g["b"])
+    u, ux, uy = (torch.zeros(len(ex), dtype=torch.float64, device="cuda") for _ in range(3))
+    g["plan"].eval_grad(W, b, t(o["sol"].c), xy, u, ux, uy)
+    torch.cuda.synchronize()
+    ou, oux, ouy = ddm.evaluate_grad(P, lay, g["W"], g["b"], o["sol"].c, ex, ey)
+    assert rel(u.cpu().numpy(), ou) <= 1e-12
+    assert rel(np.concatenate([ux.cpu().numpy(), uy.cpu().numpy()]), np.concatenate([oux, ouy])) <= 1e-12
+    # H1 seminorm of the GPU solve's gradient against the oracle solve's
+    g["plan"].eval_grad(W, b, t(g["c"]), xy, None, ux, uy)
+    torch.cuda.synchronize()
+    gg = np.concatenate([ux.cpu().numpy(), uy.cpu().numpy()])
+    assert rel(gg, np.concatenate([oux, ouy])) <= TOL_FP64

@@ -371,3 +371,23 @@ def test_planted_missing_flux_term_is_caught(monkeypatch):
     monkeypatch.setattr(ddm.sp, "csr_matrix", zero_csr)
     S_bad, _, _ = ddm.schur_system(P, lay, blocks)
     assert np.linalg.norm(S_bad - S_lit) > 1e-3 * np.linalg.norm(S_lit)
+
+
+def test_solution_gradient_matches_finite_differences_of_the_solution():
+    """grad u_h (for the H1 error of Table 2) against central differences of
+    u_h itself, at points inside subdomains (away from the box edges, where
+    the owning network changes); the value output equals evaluate()."""
+    P = tiny(2, 2, n=24)
+    lay, W, b, data = setup(P, seed=5)
+    sol = ddm.solve(P, W, b, data, lay)
+    rng = np.random.default_rng(4)
+    x = np.concatenate([rng.uniform(0.05, 0.45, 12), rng.uniform(0.55, 0.95, 12)])
+    y = np.concatenate([rng.uniform(0.55, 0.95, 12), rng.uniform(0.05, 0.45, 12)])
+    u, ux, uy = ddm.evaluate_grad(P, lay, W, b, sol.c, x, y)
+    assert np.array_equal(u, ddm.evaluate(P, lay, W, b, sol.c, x, y))
+    h = 1e-6
+    ev = lambda xx, yy: ddm.evaluate(P, lay, W, b, sol.c, xx, yy)
+    fdx = (ev(x + h, y) - ev(x - h, y)) / (2 * h)
+    fdy = (ev(x, y + h) - ev(x, y - h)) / (2 * h)
+    scale = max(np.abs(ux).max(), np.abs(uy).max())
+    assert np.abs(ux - fdx).max() <= 1e-6 * scale and np.abs(uy - fdy).max() <= 1e-6 * scale

@@ -261,6 +261,11 @@ def exact_u(problem: Problem, x, y):
     return _u_and_grad(problem, x, y)[0]
 
 
+def exact_grad(problem: Problem, x, y):
+    """(du*/dx, du*/dy) of the manufactured solution."""
+    return _u_and_grad(problem, x, y)[1:3]
+
+
 def coefficient(problem: Problem, x, y):
     """a, da/dx, da/dy of a = 1 + 0.5 sin(2 pi k1 x) cos(2 pi k2 y); a = 1 for Poisson."""
     x = np.asarray(x, dtype=np.float64)
