@@ -602,15 +602,18 @@ def main():
         except Exception:
             threads = len(os.sched_getaffinity(0))
         lay = build_layout(P)
-        Wn, bn = wl.hidden_params(P, seeds[0])
         data = ddm.problem_data(P, lay, wl.source_f, wl.boundary_g, wl.coefficient)
+        # a bounded sample: two full solves (instances 0 and 1 of the batch),
+        # about 10-15 s on the host; instance 0 is also the parity reference
+        nsamp = 2
+        params = [wl.hidden_params(P, seeds[i]) for i in range(nsamp)]
         c0 = time.perf_counter()
-        sol = ddm.solve(P, Wn, bn, data, lay)
+        sols = [ddm.solve(P, Wn, bn, data, lay) for Wn, bn in params]
         c1 = time.perf_counter()
-        oracle_ref = (sol.u_gamma, ddm.evaluate(P, lay, Wn, bn, sol.c, ex, ey))
-        cpu = {"value": 1.0 / (c1 - c0), "unit": "solves/s", "cores": int(threads), "kind": "oracle",
-               "sample": "one full FP64 oracle solve of the same 8x8 workload (hidden-layer seed %d), "
-                         "%.1f s" % (seeds[0], c1 - c0)}
+        oracle_ref = (sols[0].u_gamma, ddm.evaluate(P, lay, params[0][0], params[0][1], sols[0].c, ex, ey))
+        cpu = {"value": nsamp / (c1 - c0), "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+               "sample": "%d full FP64 oracle solves of the same 8x8 workload (hidden-layer seeds %d, %d), "
+                         "%.1f s" % (nsamp, seeds[0], seeds[1], c1 - c0)}
 
     tol = {"fp64": 1e-8, "mixed": 1e-6}
     modes = {}
