@@ -125,10 +125,12 @@ void schur_mblocks(hipStream_t st, int nblk, const int32_t* desc, const double* 
 void schur_avec(hipStream_t st, int nE, const int32_t* desc, const double* P, int ldp, long long sP,
                 int cbase, int acol, int mg, double* abuf, int ngeo, int ninst);
 // S blocks and rhs are written at the permuted edge positions perm[E].
-void schur_sblocks(hipStream_t st, int nE, int mg, const int32_t* tptr, const int32_t* tdesc,
-                   const int32_t* mptr, const int32_t* mdesc, const double* P, int ldp,
-                   long long sP, const double* Mbuf, double* S, int lds_, const int32_t* perm,
-                   int ngeo, long long sM, long long sS, int ninst);
+// nzb [nnz]: blocks E1 + E2 nE with T or M contributions (formed with
+// LDS-staged products); zb [nz]: the other blocks (written as zeros).
+void schur_sblocks(hipStream_t st, int nE, int mg, const int32_t* nzb, int nnz, const int32_t* zb, int nz,
+                   const int32_t* tptr, const int32_t* tdesc, const int32_t* mptr, const int32_t* mdesc,
+                   const double* P, int ldp, long long sP, const double* Mbuf, double* S, int lds_,
+                   const int32_t* perm, int ngeo, long long sM, long long sS, int ninst);
 void schur_rhs(hipStream_t st, int nE, int mg, const int32_t* qdesc, const int32_t* gptr,
                const int32_t* gdesc, const double* P, int ldp, long long sP, int qcol,
                const double* Mbuf, const double* abuf, double* rhs, int inc, const int32_t* perm,

@@ -1350,7 +1350,8 @@ void schur_avec(hipStream_t st, int nE, const int32_t* desc, const double* P, in
 // One workgroup per mg x mg block (E1, E2) of S:
 //   S_{E1,E2} = sum_s [delta_{E1E2} I - T_s(E1, E2)] + sum_g M_{g,E1}^T M_{g,E2}.
 // Terms are listed per block in a fixed order, so the sum is deterministic.
-__global__ __launch_bounds__(256) void schur_sblocks_kernel(int nE, int mg, const int32_t* tptr,
+__global__ __launch_bounds__(256) void schur_sblocks_kernel(int nE, int mg, const int32_t* blocks,
+                                                            const int32_t* tptr,
                                                             const int32_t* tdesc,
                                                             const int32_t* mptr,
                                                             const int32_t* mdesc, const double* P,
@@ -1360,18 +1361,20 @@ __global__ __launch_bounds__(256) void schur_sblocks_kernel(int nE, int mg, cons
                                                             long long sM, long long sS)
 {
     // M blocks staged column-major with a padded column stride (mg + 1
-    // doubles): the lanes of a wave read consecutive columns r at the same p,
-    // which a stride of mg (e.g. 40) would fold onto a few LDS banks
-    __shared__ double M1[64 * 65];
-    __shared__ double M2[64 * 65];
-    const int E1 = blockIdx.x, E2 = blockIdx.y;
+    // doubles), so that the 16 lanes of a fragment read (consecutive columns,
+    // same k) do not fold onto a few LDS banks; 2 mg (mg + 1) doubles of
+    // dynamic LDS (26 KB at mg = 40), so that several workgroups share a CU
+    extern __shared__ double schur_lds[];
+    double* M1 = schur_lds;
+    double* M2 = schur_lds + mg * (mg + 1);
+    const int blk = blocks[blockIdx.x];   // a block that receives T or M contributions
+    const int E1 = blk % nE, E2 = blk / nE;
     {
-        const long long inst = blockIdx.z;
+        const long long inst = blockIdx.y;
         P += inst * ngeo * sP;
         Mbuf += inst * sM;
         S += inst * sS;
     }
-    const int blk = E1 + E2 * nE;
     const int mm = mg * mg;
     const int tid = threadIdx.x;
     double acc[16];
@@ -1391,26 +1394,59 @@ __global__ __launch_bounds__(256) void schur_sblocks_kernel(int nE, int mg, cons
             }
         }
     }
-    for (int it = mptr[blk]; it < mptr[blk + 1]; ++it) {
-        const double* A1 = Mbuf + (long long)mdesc[2 * it] * mm;
-        const double* A2 = Mbuf + (long long)mdesc[2 * it + 1] * mm;
-        const int ms = mg + 1;
+    // M^T M contributions on the matrix cores: D = sum over pairs of A1^T A2
+    // (A = M_{g,E} blocks, column-major), the mg x mg output split into
+    // 16 x 16 tiles dealt to the four waves (tile tau = wave + 4u), k in
+    // steps of 4; lane l supplies A1[k][i], A2[k][j] with i or j = 16 t + l % 16
+    // and k = 4 ks + l / 16 (entries beyond mg are zero)
+    const int npair = mptr[blk + 1] - mptr[blk];
+    if (npair > 0) {
+        const int ms = mg + 1, nt = (mg + 15) / 16, nks = (mg + 3) / 4;
+        const int lane = tid & 63, wave = tid >> 6, lr = lane & 15, lq = lane >> 4;
+        v4d macc[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) macc[u] = (v4d){0.0, 0.0, 0.0, 0.0};
+        for (int it = mptr[blk]; it < mptr[blk + 1]; ++it) {
+            const double* A1 = Mbuf + (long long)mdesc[2 * it] * mm;
+            const double* A2 = Mbuf + (long long)mdesc[2 * it + 1] * mm;
+            __syncthreads();
+            for (int idx = tid; idx < mm; idx += 256) {
+                const int q = (idx / mg) * ms + idx % mg;
+                M1[q] = A1[idx];
+                M2[q] = A2[idx];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int tau = wave + 4 * u;
+                if (tau >= nt * nt) continue;
+                const int i = 16 * (tau % nt) + lr, j = 16 * (tau / nt) + lr;
+                for (int ks = 0; ks < nks; ++ks) {
+                    const int k = 4 * ks + lq;
+                    const double a = (i < mg && k < mg) ? M1[i * ms + k] : 0.0;
+                    const double b = (j < mg && k < mg) ? M2[j * ms + k] : 0.0;
+                    macc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, macc[u], 0, 0, 0);
+                }
+            }
+        }
+        // through LDS (column-major, stride ms) back to the element layout of acc
         __syncthreads();
-        for (int idx = tid; idx < mm; idx += 256) {
-            const int q = (idx / mg) * ms + idx % mg;
-            M1[q] = A1[idx];
-            M2[q] = A2[idx];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int tau = wave + 4 * u;
+            if (tau >= nt * nt) continue;
+            const int j = 16 * (tau / nt) + lr;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = 16 * (tau % nt) + 4 * r + lq;
+                if (i < mg && j < mg) M1[j * ms + i] = macc[u][r];
+            }
         }
         __syncthreads();
 #pragma unroll
         for (int t = 0; t < 16; ++t) {
             const int idx = tid + 256 * t;
-            if (idx < mm) {
-                const int r = idx % mg, c = idx / mg;
-                double v = 0.0;
-                for (int p = 0; p < mg; ++p) v += M1[r * ms + p] * M2[c * ms + p];
-                acc[t] += v;
-            }
+            if (idx < mm) acc[t] += M1[(idx / mg) * ms + idx % mg];
         }
     }
 #pragma unroll
@@ -1423,14 +1459,33 @@ __global__ __launch_bounds__(256) void schur_sblocks_kernel(int nE, int mg, cons
     }
 }
 
-void schur_sblocks(hipStream_t st, int nE, int mg, const int32_t* tptr, const int32_t* tdesc,
-                   const int32_t* mptr, const int32_t* mdesc, const double* P, int ldp,
-                   long long sP, const double* Mbuf, double* S, int lds, const int32_t* perm,
-                   int ngeo, long long sM, long long sS, int ninst)
+// The blocks of S that no subdomain touches are zero: written by a plain fill
+// kernel (no LDS, so many workgroups run at once) instead of by the product
+// kernel above.
+__global__ __launch_bounds__(256) void schur_zero_kernel(int nE, int mg, const int32_t* blocks, double* S, int lds,
+                                                         const int32_t* perm, long long sS)
 {
-    if (nE <= 0) return;
-    hipLaunchKernelGGL(schur_sblocks_kernel, dim3(nE, nE, ninst), dim3(256), 0, st, nE, mg, tptr,
-                       tdesc, mptr, mdesc, P, ldp, sP, Mbuf, S, lds, perm, ngeo, sM, sS);
+    const int blk = blocks[blockIdx.x];
+    const int E1 = blk % nE, E2 = blk / nE;
+    S += (long long)blockIdx.y * sS;
+    const int mm = mg * mg;
+    for (int idx = threadIdx.x; idx < mm; idx += 256) {
+        const int r = idx % mg, c = idx / mg;
+        S[(long long)(perm[E2] * mg + c) * lds + (perm[E1] * mg + r)] = 0.0;
+    }
+}
+
+void schur_sblocks(hipStream_t st, int nE, int mg, const int32_t* nzb, int nnz, const int32_t* zb, int nz,
+                   const int32_t* tptr, const int32_t* tdesc, const int32_t* mptr, const int32_t* mdesc,
+                   const double* P, int ldp, long long sP, const double* Mbuf, double* S, int lds,
+                   const int32_t* perm, int ngeo, long long sM, long long sS, int ninst)
+{
+    if (nE <= 0 || ninst <= 0) return;
+    if (nnz > 0)
+        hipLaunchKernelGGL(schur_sblocks_kernel, dim3(nnz, ninst), dim3(256), 2 * mg * (mg + 1) * sizeof(double), st,
+                           nE, mg, nzb, tptr, tdesc, mptr, mdesc, P, ldp, sP, Mbuf, S, lds, perm, ngeo, sM, sS);
+    if (nz > 0)
+        hipLaunchKernelGGL(schur_zero_kernel, dim3(nz, ninst), dim3(256), 0, st, nE, mg, zb, S, lds, perm, sS);
 }
 
 // rhs_E = sum_s q_s(E) - sum_g M_{g,E}^T a_g.

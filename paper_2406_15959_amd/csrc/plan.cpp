@@ -98,6 +98,9 @@ struct elmddm_plan {
     int32_t *d_kind = nullptr, *d_src = nullptr, *d_cmap = nullptr, *d_gidx = nullptr;
     int32_t *d_mdesc = nullptr, *d_adesc = nullptr, *d_tptr = nullptr, *d_tdesc = nullptr;
     int32_t *d_mptr = nullptr, *d_mlist = nullptr, *d_qdesc = nullptr, *d_gptr = nullptr;
+    int32_t *d_nzb = nullptr, *d_zb = nullptr;   // S blocks with / without contributions
+    int32_t* d_zb_env = nullptr;                 // the zero blocks the envelope factorisation reads
+    int n_nzb = 0, n_zb = 0, n_zb_env = 0;
     int32_t *d_gdesc = nullptr;
     int n_mblocks = 0;
     DevInfo* d_info = nullptr;
@@ -459,6 +462,8 @@ elmddm_status build(elmddm_plan* P)
     std::vector<int32_t> ident(std::max(P->nE, 1));
     for (int e = 0; e < P->nE; ++e) ident[e] = e;
     const size_t nEE = P->mfree ? 0 : (size_t)P->nE * P->nE;
+    if (nEE > (size_t)INT32_MAX)
+        return fail(ELMDDM_UNSUPPORTED, "too many interface edges for a dense interface system (use MATRIX_FREE)");
     std::vector<std::vector<int32_t>> tl(nEE), ml(nEE);
     for (int s = 0; s < N && !P->mfree; ++s)
         for (auto& e1 : sub_edges[s])
@@ -479,12 +484,16 @@ elmddm_status build(elmddm_plan* P)
             }
         }
     std::vector<int32_t> tptr(nEE + 1, 0), mptr(nEE + 1, 0), tdesc, mlist, gptr(P->nE + 1, 0), gdesc;
+    std::vector<int32_t> nzb, zb, zb_env;
     for (size_t b = 0; b < nEE; ++b) {
         tptr[b + 1] = tptr[b] + (int32_t)(tl[b].size() / 4);
         mptr[b + 1] = mptr[b] + (int32_t)(ml[b].size() / 2);
         tdesc.insert(tdesc.end(), tl[b].begin(), tl[b].end());
         mlist.insert(mlist.end(), ml[b].begin(), ml[b].end());
+        (tl[b].empty() && ml[b].empty() ? zb : nzb).push_back((int32_t)b);
     }
+    P->n_nzb = (int)nzb.size();
+    P->n_zb = (int)zb.size();
     for (int e = 0; e < P->nE; ++e) {
         gptr[e + 1] = gptr[e] + (int32_t)(gl[e].size() / 2);
         gdesc.insert(gdesc.end(), gl[e].begin(), gl[e].end());
@@ -534,6 +543,17 @@ elmddm_status build(elmddm_plan* P)
             while (c < j0 && env[c] < j0) ++c;
             P->kbeg[pb] = c;
         }
+        // Zero blocks that the envelope factorisation reads: some (row, col)
+        // of the block with col <= row < rend[col / NB].  The others are never
+        // read unless the caller keeps S (then every block is written).
+        for (int32_t b : zb) {
+            const int pr = perm[b % P->nE] * mg, pc = perm[b / P->nE] * mg;
+            bool need = false;
+            for (int col = pc; col < pc + mg && !need; ++col)
+                need = std::max(pr, col) < std::min(pr + mg, P->rend[col / NB]);
+            if (need) zb_env.push_back(b);
+        }
+        P->n_zb_env = (int)zb_env.size();
     }
 
     // ---- device allocations ----
@@ -560,6 +580,9 @@ elmddm_status build(elmddm_plan* P)
     TRY(P->upload(&P->d_tdesc, tdesc));
     TRY(P->upload(&P->d_mptr, mptr));
     TRY(P->upload(&P->d_mlist, mlist));
+    TRY(P->upload(&P->d_nzb, nzb));
+    TRY(P->upload(&P->d_zb, zb));
+    TRY(P->upload(&P->d_zb_env, zb_env));
     TRY(P->upload(&P->d_gptr, gptr));
     TRY(P->upload(&P->d_gdesc, gdesc));
     TRY(P->upload(&P->d_perm, perm));
@@ -1050,8 +1073,11 @@ elmddm_status elmddm_solve(elmddm_plan* P, const double* W, const double* b, con
                 hipSuccess)
                 return check_launch("CG result copy");
         } else {
-            schur_sblocks(st, P->nE, P->mg, P->d_tptr, P->d_tdesc, P->d_mptr, P->d_mlist, P->P, P->ldp,
-                          P->sP, P->Mbuf, P->Sx, P->lds, P->d_perm, P->N, sM, sS, B);
+            // a kept S is copied whole: then every zero block is written
+            const bool all_zero = P->keep_schur && P->Skeep;
+            schur_sblocks(st, P->nE, P->mg, P->d_nzb, P->n_nzb, all_zero ? P->d_zb : P->d_zb_env,
+                          all_zero ? P->n_zb : P->n_zb_env, P->d_tptr, P->d_tdesc, P->d_mptr, P->d_mlist, P->P,
+                          P->ldp, P->sP, P->Mbuf, P->Sx, P->lds, P->d_perm, P->N, sM, sS, B);
             schur_rhs(st, P->nE, P->mg, P->d_qdesc, P->d_gptr, P->d_gdesc, P->P, P->ldp, P->sP, P->kpad,
                       P->Mbuf, P->abuf, P->yvec, 1, P->d_perm, P->N, sM, (long long)P->nE * P->mg,
                       P->nG, B);
