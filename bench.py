@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Throughput of the DDM-ELM hot path on one MI355X.
 
-One step = one batched solve of B instances (default 32) of the 8x8 Poisson
+One step = one batched solve of B instances (default 64) of the 8x8 Poisson
 workload, each a complete Algorithm 1 of the paper (feature assembly,
 batched local least squares, interface Schur complement formation and
 solve, back-solve of every local output layer): 64 subdomains, 400 tanh
@@ -33,7 +33,7 @@ sys.path.insert(0, ROOT)
 MFMA_F64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
 MFMA_F32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
 HBM_PEAK_GBS = 8000.0
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "gram_8x8_fp64_batch32_pmc.txt")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "gram_8x8_fp64_batch64_pmc.txt")
 
 
 def gram_source_sha():
@@ -498,7 +498,7 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the 32x32 leg")
     ap.add_argument("--no-init", action="store_true",
                     help="skip the initialisation study and the accuracy table (Tables 1 and 2 style)")
-    ap.add_argument("--batch", type=int, default=32, help="problem instances solved together per step")
+    ap.add_argument("--batch", type=int, default=64, help="problem instances solved together per step")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration) and exit")
     args = ap.parse_args()
