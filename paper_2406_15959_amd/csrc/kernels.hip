@@ -297,12 +297,15 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(
             if constexpr ((MK & 5) != 0) bv[ks][0] = Bs(k, wn * 32 + lr);
             if constexpr ((MK & 10) != 0) bv[ks][1] = Bs(k, wn * 32 + 16 + lr);
         }
+        // The instruction multiplies op(B)^T op(A)^T: its result is the
+        // transposed C block, so that a lane's accumulator runs along a
+        // column of C (see the store below).
 #pragma unroll
         for (int ks = 0; ks < GB_K / 4; ++ks) {
-            if constexpr ((MK & 1) != 0) acc[0][0] = mma(av[ks][0], bv[ks][0], acc[0][0]);
-            if constexpr ((MK & 2) != 0) acc[0][1] = mma(av[ks][0], bv[ks][1], acc[0][1]);
-            if constexpr ((MK & 4) != 0) acc[1][0] = mma(av[ks][1], bv[ks][0], acc[1][0]);
-            if constexpr ((MK & 8) != 0) acc[1][1] = mma(av[ks][1], bv[ks][1], acc[1][1]);
+            if constexpr ((MK & 1) != 0) acc[0][0] = mma(bv[ks][0], av[ks][0], acc[0][0]);
+            if constexpr ((MK & 2) != 0) acc[0][1] = mma(bv[ks][1], av[ks][0], acc[0][1]);
+            if constexpr ((MK & 4) != 0) acc[1][0] = mma(bv[ks][0], av[ks][1], acc[1][0]);
+            if constexpr ((MK & 8) != 0) acc[1][1] = mma(bv[ks][1], av[ks][1], acc[1][1]);
         }
     };
     const int nk = (kend > kbeg) ? (kend - kbeg + GB_K - 1) / GB_K : 0;
@@ -345,6 +348,9 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(
             }
         }
     }
+    // acc[bi][bj] holds the transposed 16 x 16 block: C row = lane % 16, so
+    // the 16 lanes of a quarter-wave store one contiguous 128-byte column
+    // segment of C.
     const int lq = lane >> 4;
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
@@ -353,8 +359,8 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 if (!(wmask & (1 << (2 * bi + bj)))) continue;
-                const int row = m0 + wm * 32 + bi * 16 + (F64 ? r * 4 + lq : lq * 4 + r);
-                const int col = n0 + wn * 32 + bj * 16 + lr;
+                const int row = m0 + wm * 32 + bi * 16 + lr;
+                const int col = n0 + wn * 32 + bj * 16 + (F64 ? r * 4 + lq : lq * 4 + r);
                 if (row < M && col < N) {
                     const long long ci = (long long)col * ldc + row;
                     double v = alpha * (double)acc[bi][bj][r];
