@@ -148,7 +148,7 @@ __device__ __forceinline__ bool aligned16(const double* p)
 // l is D[4*(l/16) + r][l%16].  LDS rows are padded so that the four k rows a
 // wave reads at once fall in different banks (for FP64: the two 16-lane
 // groups of each half-wave).
-template <class CT, bool TA, bool TB, int KMODE, bool LOWER, int GB_K, bool XCD>
+template <class CT, bool TA, bool TB, int KMODE, bool LOWER, int GB_K, bool XCD, bool CPRE = false>
 __global__ __launch_bounds__(256) void gemm_mfma_kernel(
     int M, int N, int K, double alpha, const double* A, int lda, long long sA, const double* B,
     int ldb, long long sB, double beta, double* C, int ldc, long long sC)
@@ -308,6 +308,28 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(
             if constexpr ((MK & 8) != 0) acc[1][1] = mma(bv[ks][1], av[ks][1], acc[1][1]);
         }
     };
+    // acc[bi][bj] holds the transposed 16 x 16 block: C row = lane % 16, so
+    // the 16 lanes of a quarter-wave read and write one contiguous 128-byte
+    // column segment of C.  With CPRE (chosen by the launcher when beta != 0)
+    // the C values are fetched before the K loop, so that their latency hides
+    // behind it (short-K updates); the beta = 0 instances keep the registers.
+    const int lq = lane >> 4;
+    auto crow = [&](int bi) { return m0 + wm * 32 + bi * 16 + lr; };
+    auto ccol = [&](int bj, int r) { return n0 + wn * 32 + bj * 16 + (F64 ? r * 4 + lq : lq * 4 + r); };
+    double cpre[2][2][4];
+    if constexpr (CPRE) {
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = crow(bi), col = ccol(bj, r);
+                    cpre[bi][bj][r] = ((wmask & (1 << (2 * bi + bj))) && row < M && col < N)
+                                          ? C[(long long)col * ldc + row]
+                                          : 0.0;
+                }
+    }
     const int nk = (kend > kbeg) ? (kend - kbeg + GB_K - 1) / GB_K : 0;
     if (nk > 0) {
         load(kbeg);
@@ -348,10 +370,6 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(
             }
         }
     }
-    // acc[bi][bj] holds the transposed 16 x 16 block: C row = lane % 16, so
-    // the 16 lanes of a quarter-wave store one contiguous 128-byte column
-    // segment of C.
-    const int lq = lane >> 4;
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -359,12 +377,12 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 if (!(wmask & (1 << (2 * bi + bj)))) continue;
-                const int row = m0 + wm * 32 + bi * 16 + lr;
-                const int col = n0 + wn * 32 + bj * 16 + (F64 ? r * 4 + lq : lq * 4 + r);
+                const int row = crow(bi), col = ccol(bj, r);
                 if (row < M && col < N) {
                     const long long ci = (long long)col * ldc + row;
                     double v = alpha * (double)acc[bi][bj][r];
-                    if (beta != 0.0) v += beta * C[ci];
+                    if constexpr (CPRE) v += beta * cpre[bi][bj][r];
+                    else if (beta != 0.0) v += beta * C[ci];
                     C[ci] = v;
                 }
             }
@@ -386,8 +404,12 @@ static void gemm_launch(hipStream_t st, int M, int N, int K, double alpha, const
 {
     dim3 grid((M + GB_M - 1) / GB_M, (N + GB_N - 1) / GB_N, batch);
     if (LOWER && M == N) grid = dim3(grid.x * (grid.x + 1) / 2, 1, batch);   // lower tiles only
-    hipLaunchKernelGGL((gemm_mfma_kernel<CT, TA, TB, KMODE, LOWER, BK, XCD>), grid, dim3(256), 0, st, M,
-                       N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+    if (beta != 0.0)
+        hipLaunchKernelGGL((gemm_mfma_kernel<CT, TA, TB, KMODE, LOWER, BK, XCD, true>), grid, dim3(256), 0, st,
+                           M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+    else
+        hipLaunchKernelGGL((gemm_mfma_kernel<CT, TA, TB, KMODE, LOWER, BK, XCD>), grid, dim3(256), 0, st, M,
+                           N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
 }
 
 template <bool TA, bool TB, int KMODE, bool LOWER>
