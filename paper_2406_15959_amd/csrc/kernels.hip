@@ -815,7 +815,9 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* A, int lda, lon
     const int w = tid >> 6;
     const int lr = lane & 15, lq = lane >> 4;
     if (tid == 0) bad_any = 0;
-    for (int idx = tid; idx < 64 * 64; idx += 256) {
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {   // 64 x 64 tile, 256 threads
+        const int idx = tid + 256 * it;
         const int c = idx >> 6, r = idx & 63;   // column-major walk: coalesced loads
         double v = (r == c) ? 1.0 : 0.0;
         if (r < jb && c < jb && r >= c) v = A[(long long)(j + c) * lda + (j + r)];
@@ -975,7 +977,9 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* A, int lda, lon
             rhs[j + tid] = acc;
         }
     }
-    for (int idx = tid; idx < 64 * 64; idx += 256) {
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {   // 64 x 64 tile, 256 threads
+        const int idx = tid + 256 * it;
         const int c = idx >> 6, r = idx & 63;
         const bool in = (r < jb) && (c < jb);
         const double xv = (in && c <= r) ? Xs[r][c] : 0.0;
@@ -1039,7 +1043,9 @@ __global__ __launch_bounds__(256) void envelope_step_kernel(double* A, int lda, 
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1;
     const int lr = lane & 15, lq = lane >> 4;
-    for (int idx = tid; idx < 64 * 64; idx += 256) {
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {   // 64 x 64 tile, 256 threads
+        const int idx = tid + 256 * it;
         const int c = idx >> 6, r = idx & 63;
         Dv[r][c] = (r < jb && c < jb) ? Dinv[c * 64 + r] : 0.0;
         S1[r][c] = (I + r < r1 && c < jb) ? A[(long long)(j + c) * lda + I + r] : 0.0;
@@ -1097,7 +1103,9 @@ __global__ __launch_bounds__(256) void envelope_step_kernel(double* A, int lda, 
                 if (row < r1 && col < r1) A[(long long)col * lda + row] -= acc[u][v][r];
             }
     if (a == b) {
-        for (int idx = tid; idx < 64 * 64; idx += 256) {
+#pragma unroll
+        for (int it = 0; it < 16; ++it) {   // 64 x 64 tile, 256 threads
+            const int idx = tid + 256 * it;
             const int c = idx >> 6, r = idx & 63;
             if (I + r < r1 && c < jb) Lo[(long long)(j + c) * ldo + I + r] = S1[r][c];
         }
@@ -1143,7 +1151,9 @@ __global__ __launch_bounds__(256) void envelope_panel_kernel(const double* A, in
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1;
     const int lr = lane & 15, lq = lane >> 4;
-    for (int idx = tid; idx < 64 * 64; idx += 256) {
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {   // 64 x 64 tile, 256 threads
+        const int idx = tid + 256 * it;
         const int c = idx >> 6, r = idx & 63;
         Dv[r][c] = (r < jb && c < jb) ? Dinv[c * 64 + r] : 0.0;
         S1[r][c] = (I + r < r1 && c < jb) ? A[(long long)(j + c) * lda + I + r] : 0.0;
@@ -1170,7 +1180,9 @@ __global__ __launch_bounds__(256) void envelope_panel_kernel(const double* A, in
 #pragma unroll
             for (int r = 0; r < 4; ++r) S1[wm * 32 + u * 16 + 4 * r + lq][wn * 32 + v * 16 + lr] = acc[u][v][r];
     __syncthreads();
-    for (int idx = tid; idx < 64 * 64; idx += 256) {
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {   // 64 x 64 tile, 256 threads
+        const int idx = tid + 256 * it;
         const int c = idx >> 6, r = idx & 63;
         if (I + r < r1 && c < jb) Lo[(long long)(j + c) * ldo + I + r] = S1[r][c];
     }
