@@ -638,15 +638,17 @@ def main():
 
     # Roofline of the dominant kernel: the batched FP64 MFMA Gram (SYRK)
     # launch of CholeskyQR passes 2 and 3, timed in the reported (mixed) run.
-    # Algorithmic work per launch: sum over subdomains of m_s * n * (n + 1)
-    # flops (symmetric product, lower triangle).
+    # Algorithmic work per launch: sum over subdomains of m_s * c * (c + 1)
+    # flops (symmetric product, lower triangle) with c = n columns in pass 2
+    # and c = n + 1 in the last pass (its Gram includes the column F).
     m_rows = P.q_x * P.q_y + 4 * P.m_ifc_edge if P.m_ifc_edge == P.m_bdry_edge else s.max_rows
     n = P.neurons
     flops_per_launch = nb * P.nsub * m_rows * n * (n + 1)
+    flops_last = nb * P.nsub * m_rows * (n + 1) * (n + 2)
     mixed = runs["mixed"]
     gram64_ms = 0.5 * (mixed["pass_ms"][1][0] + mixed["pass_ms"][2][0])
     gram32_ms = mixed["pass_ms"][0][0]
-    achieved = flops_per_launch / (gram64_ms * 1e-3) / 1e12 if gram64_ms > 0 else 0.0
+    achieved = 0.5 * (flops_per_launch + flops_last) / (gram64_ms * 1e-3) / 1e12 if gram64_ms > 0 else 0.0
     kname = ("gemm_strip_kernel<T=%d>" % tuned[0]) if tuned[0] >= 4 else ("gemm_mfma_kernel<double> variant %d" % (-1 - tuned[0]))
     roofline = {"bound": "mfma", "kernel": "FP64 Gram product, " + kname,
                 "achieved": achieved, "peak": MFMA_F64_PEAK_TFLOPS, "unit": "TFLOP/s",

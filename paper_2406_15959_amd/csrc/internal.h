@@ -76,9 +76,6 @@ void trsm_strip(hipStream_t st, int T, int rows, int n, const double* X, int ldx
                 const double* Linv, int ldl, long long sL, double* Y, long long sY, int batch);
 void strip_gemm_nn(hipStream_t st, int T, int M, int N, int K, const double* A, int lda,
                    const double* B, int ldb, double* C, int ldc);
-// Row n of an extended Gram matrix: G[n][c] = X[:, c] . X[:, n] for c < n.
-void gram_rhs_row(hipStream_t st, const double* X, int ldx, long long sX, int rows, int n, double* G,
-                  int ldg, long long sG, int batch);
 
 // Writes X (plan layout, ldx rows x (n+1) columns per subdomain) or, if Kout != nullptr,
 // the compact K^s [n][ldK], A^s [n][ldD] and F^s [ldF] per subdomain.

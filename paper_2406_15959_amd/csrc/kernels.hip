@@ -726,30 +726,6 @@ void strip_gemm_nn(hipStream_t st, int T, int M, int N, int K, const double* A, 
     strip_dispatch<false, false, 0, false>(T, st, M, N, K, 1.0, A, lda, 0, B, ldb, 0, 0.0, C, ldc, 0, 1);
 }
 
-// G[n + c*ldg] = sum_r X[r][c] X[r][n]: the rhs row F^T Q of an extended Gram matrix.
-__global__ __launch_bounds__(256) void gram_rhs_row_kernel(const double* X, int ldx, long long sX,
-                                                           int rows, int n, double* G, int ldg,
-                                                           long long sG)
-{
-    const long long z = blockIdx.y;
-    const int lane = threadIdx.x & 63;
-    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (c >= n) return;
-    const double* xc = X + z * sX + (long long)c * ldx;
-    const double* xf = X + z * sX + (long long)n * ldx;
-    double v = 0.0;
-    for (int r = lane; r < rows; r += 64) v += xc[r] * xf[r];
-    v = wave_sum(v);
-    if (lane == 0) G[z * sG + (long long)c * ldg + n] = v;
-}
-
-void gram_rhs_row(hipStream_t st, const double* X, int ldx, long long sX, int rows, int n, double* G,
-                  int ldg, long long sG, int batch)
-{
-    dim3 grid((n + 3) / 4, batch);
-    hipLaunchKernelGGL(gram_rhs_row_kernel, grid, dim3(256), 0, st, X, ldx, sX, rows, n, G, ldg, sG);
-}
-
 // ---------------------------------------------------------------------------
 // Cholesky pieces.
 // ---------------------------------------------------------------------------

@@ -1015,12 +1015,14 @@ elmddm_status elmddm_solve(elmddm_plan* P, const double* W, const double* b, con
         const bool last = pass == np;
         const int ncol = last ? n + 1 : n;
         if (P->timing) (void)hipEventRecord(P->pev[3 * (pass - 1)], st);
+        // The last pass takes the Gram of [Q F] (F is column n): its row n is
+        // the right-hand side row F^T Q that the factorisation turns into h
+        // (n + 1 columns fall in the same 64-wide tiles as n unless n % 64 == 0).
         if (pass == 1 && mixed)
             gram_product_f32(st, n, P->gram_rows, src, ldx, P->sX, P->G, ldg, P->sG, N);
         else
-            gram_product(st, P->gram_code, n, P->gram_rows, src, ldx, P->sX, P->G, ldg, P->sG, N);
+            gram_product(st, P->gram_code, last ? n + 1 : n, P->gram_rows, src, ldx, P->sX, P->G, ldg, P->sG, N);
         if (P->timing) (void)hipEventRecord(P->pev[3 * (pass - 1) + 1], st);
-        if (last) gram_rhs_row(st, src, ldx, P->sX, P->gram_rows, n, P->G, ldg, P->sG, N);
         if (pass <= np - 2) scale_diag(st, P->G, ldg, P->sG, n, 1.0 + (pass == 1 && mixed ? shift32 : shift64), N);
         // breakdown threshold on pivot / original diagonal: 64 n u, except for
         // the unshifted middle pass of the mixed mode, whose input has
