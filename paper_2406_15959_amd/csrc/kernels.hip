@@ -56,6 +56,20 @@ __global__ __launch_bounds__(256) void assemble_kernel(
     const long long inst = s / ngeo;     // its problem instance
     const int r = blockIdx.x * 64 + (threadIdx.x & 63);
     const int cg = threadIdx.x >> 6;
+    const int c0 = blockIdx.y * 64;
+    // hidden-layer parameters of this block's 64 columns, read once into LDS
+    // (a load per column inside the loop below would wait on memory each time)
+    __shared__ double wsh[3][64];
+    if (threadIdx.x < 64) {
+        const int col = c0 + threadIdx.x;
+        if (col < n) {
+            const long long wi = (long long)s * n + col;
+            wsh[0][threadIdx.x] = W[2 * wi];
+            wsh[1][threadIdx.x] = W[2 * wi + 1];
+            wsh[2][threadIdx.x] = bias[wi];
+        }
+    }
+    __syncthreads();
     if (r >= ldx) return;
     const long long ri = (long long)sg * ldx + r;
     const int kind = rows.kind[ri];
@@ -72,7 +86,6 @@ __global__ __launch_bounds__(256) void assemble_kernel(
         ay = coef[2 * coef_stride + src];
     }
     const int crow = compact ? rows.cmap[ri] : -1;
-    const int c0 = blockIdx.y * 64;
     for (int cc = cg; cc < 64; cc += 4) {
         const int col = c0 + cc;
         if (col > n) break;
@@ -81,11 +94,10 @@ __global__ __launch_bounds__(256) void assemble_kernel(
             if (kind == ROW_INTERIOR) v = f[src];
             else if (kind == ROW_BOUNDARY) v = g[src];
         } else if (kind != ROW_ZERO) {
-            const long long wi = (long long)s * n + col;
-            const double w0 = W[2 * wi], w1 = W[2 * wi + 1];
+            const double w0 = wsh[0][cc], w1 = wsh[1][cc];
             const double wx = w0 * geom.sx;
             const double wy = w1 * geom.sy;
-            const double z = w0 * xh + w1 * yh + bias[wi];
+            const double z = w0 * xh + w1 * yh + wsh[2][cc];
             const double t = tanh_feat(z);
             const double d1 = 1.0 - t * t;
             if (kind == ROW_INTERIOR) {
