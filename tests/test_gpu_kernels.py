@@ -27,6 +27,7 @@ def hooks(gpu):
     L.elmddm_test_mfma_layout_f32.argtypes = [vp, vp, vp, vp]
     L.elmddm_test_gram_f32.argtypes = [i32, i32, vp, i32, i64, vp, i32, i64, i32, vp]
     L.elmddm_test_gram.argtypes = [i32, i32, i32, vp, i32, i64, vp, i32, i64, i32, vp]
+    L.elmddm_test_set_gemm_variant.argtypes = [i32, i32]
     return L
 
 
@@ -129,12 +130,27 @@ def structured_B(B, tb, kmode, K, N):
     return B * (keep.T if tb else keep)
 
 
+# Kernel variants: K depth 16 (double-buffered LDS) or 32, tile order plain or
+# XCD-grouped; every case runs on each.  Odd M gives beta != 0, which takes
+# the instance that reads C before the K loop.
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 @pytest.mark.parametrize("ta,tb,kmode,lower,M,N,K,batch", [
     (0, 0, 0, 0, 70, 33, 129, 2), (0, 1, 0, 0, 64, 64, 64, 1), (1, 0, 0, 0, 100, 90, 37, 3),
     (1, 1, 0, 0, 17, 130, 16, 1), (1, 0, 0, 1, 150, 150, 300, 2), (0, 1, 0, 1, 131, 130, 64, 2),
     (0, 0, 1, 0, 40, 200, 200, 2), (0, 1, 2, 0, 300, 150, 150, 2), (0, 1, 0, 0, 1, 64, 64, 3),
+    (0, 0, 1, 0, 41, 150, 150, 2), (0, 1, 2, 0, 301, 150, 150, 2), (1, 0, 0, 1, 97, 97, 45, 2),
 ])
-def test_gemm_matches_numpy(hooks, ta, tb, kmode, lower, M, N, K, batch):
+def test_gemm_matches_numpy(hooks, variant, ta, tb, kmode, lower, M, N, K, batch):
+    hooks.elmddm_test_set_gemm_variant(0, variant)
+    hooks.elmddm_test_set_gemm_variant(1, variant)
+    try:
+        _check_gemm(hooks, ta, tb, kmode, lower, M, N, K, batch)
+    finally:
+        hooks.elmddm_test_set_gemm_variant(0, 1)   # the library's defaults
+        hooks.elmddm_test_set_gemm_variant(1, 0)
+
+
+def _check_gemm(hooks, ta, tb, kmode, lower, M, N, K, batch):
     import torch
     rng = np.random.default_rng(M * 7 + N + K)
     # math-orientation arrays, stored column-major => pass transposes as C-contiguous
