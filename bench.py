@@ -655,7 +655,7 @@ def main():
                 "frac": achieved / MFMA_F64_PEAK_TFLOPS, "traffic": measured_traffic(tuned[0], nb),
                 "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "avg_launch_ms": gram64_ms,
-                "f32_gram": {"kernel": "gemm_mfma_kernel<float> (pass 1, mixed mode)",
+                "f32_gram": {"kernel": "gram_f32_kernel (pass 1, mixed mode)",
                              "achieved": flops_per_launch / (gram32_ms * 1e-3) / 1e12 if gram32_ms > 0 else 0.0,
                              "peak": MFMA_F32_PEAK_TFLOPS, "unit": "TFLOP/s", "avg_launch_ms": gram32_ms}}
     roofline["f32_gram"]["frac"] = roofline["f32_gram"]["achieved"] / MFMA_F32_PEAK_TFLOPS

@@ -134,7 +134,9 @@ void assemble(hipStream_t st, int N, int ngeo, long long nbnd, int ldx, int n, c
 
 // ---------------------------------------------------------------------------
 // Batched GEMM on the matrix cores: C = alpha op(A) op(B) + beta C, FP64
-// operands and result, computed in FP64 (or, for the mixed-precision Gram, FP32).
+// operands and result, computed in FP64 (CT = float rounds the staged
+// operands to FP32 and accumulates in FP32; the mixed-precision Gram has a
+// kernel of its own, gram_f32_kernel).
 // Workgroup tile 64x64, K staged 16 (double-buffered) or 32 at a time
 // through LDS, four waves in a 2x2 arrangement, each wave a 32x32 block of
 // 2x2 V_MFMA_F64_16X16X4 tiles.
@@ -712,12 +714,136 @@ void gram_product(hipStream_t st, int code, int n, int rows, const double* X, in
 
 // Gram product with FP32 operands and FP32 accumulation (lower triangle,
 // widened to FP64): the first, shifted pass of the mixed-precision mode.
+// Workgroup tile 128 x 128 (lower tiles only, XCD-grouped order), eight waves
+// in 2 (rows) x 4 (columns), each a 64 x 32 block of 4 x 2 V_MFMA_F32_16X16X4
+// tiles (32 accumulator floats per lane).  FP64 operands are loaded 4 k at a
+// time per thread (row tid / 4), rounded to FP32 into a double-buffered LDS
+// stage of K depth 16 (row stride 20 floats).  The FP32 accumulators take
+// half the registers of FP64 ones, which is what makes the larger tile (half
+// the operand bytes per flop of a 64 x 64 tile) affordable; measured at the
+// 8x8 Gram shape, batch 64: 16.5 ms against 18.5 ms for the 64 x 64 kernel.
+__global__ __launch_bounds__(512) void gram_f32_kernel(int M, int K, const double* X, int ldx, long long sX,
+                                                       double* G, int ldg, long long sG)
+{
+    constexpr int TM = 128, BKK = 16, SK = BKK + 4, V = BKK / 4;
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    const unsigned gx = gridDim.x;
+    const unsigned total = gx * gridDim.y * gridDim.z;
+    const unsigned p = blockIdx.x + gx * (blockIdx.y + gridDim.y * blockIdx.z);
+    const unsigned q = (total & 7u) ? p : (p & 7u) * (total >> 3) + (p >> 3);
+    const long long z = q / gx;
+    int t = q % gx;
+    const int g = (TM + M - 1) / TM;
+    int tn = 0;
+    while (t >= g - tn) {   // lower tiles, column by column
+        t -= g - tn;
+        ++tn;
+    }
+    const int tm = tn + t;
+    X += z * sX;
+    G += z * sG;
+    const int m0 = tm * TM, n0 = tn * TM;
+    __shared__ __attribute__((aligned(16))) float As_[2][TM * SK];
+    __shared__ __attribute__((aligned(16))) float Bs_[2][TM * SK];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int lr = lane & 15, lk = lane >> 4;
+    v4f acc[4][2];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) acc[u][v] = (v4f){0.f, 0.f, 0.f, 0.f};
+    double ra[V], rb[V];
+    auto ld = [&](double (&r)[V], int mm, int kk) {
+        const double* pp = X + (long long)mm * ldx + kk;
+        if (mm < M && kk + V - 1 < K && aligned16(pp)) {
+#pragma unroll
+            for (int e = 0; e < V / 2; ++e) {
+                const double2 vv = reinterpret_cast<const double2*>(pp)[e];
+                r[2 * e] = vv.x;
+                r[2 * e + 1] = vv.y;
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < V; ++e) r[e] = (mm < M && kk + e < K) ? pp[e] : 0.0;
+        }
+    };
+    auto load = [&](int k0) {
+        const int kk = k0 + (tid & 3) * V;
+        ld(ra, m0 + (tid >> 2), kk);
+        ld(rb, n0 + (tid >> 2), kk);
+    };
+    auto store = [&](int b) {
+        const int m = tid >> 2, k = (tid & 3) * V;
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            As_[b][m * SK + k + e] = (float)ra[e];
+            Bs_[b][m * SK + k + e] = (float)rb[e];
+        }
+    };
+    // 16 x 16 blocks of this wave inside the matrix and on or below the diagonal
+    int wmask = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            const int R0 = m0 + wm * 64 + u * 16, C0 = n0 + wn * 32 + v * 16;
+            if (R0 < M && C0 < M && R0 + 15 >= C0) wmask |= 1 << (2 * u + v);
+        }
+    const int nk = (K + BKK - 1) / BKK;
+    if (nk > 0) {
+        load(0);
+        store(0);
+    }
+    __syncthreads();
+    for (int it = 0; it < nk; ++it) {
+        const int cb = it & 1;
+        if (it + 1 < nk) load((it + 1) * BKK);
+        if (wmask) {
+#pragma unroll
+            for (int ks = 0; ks < BKK / 4; ++ks) {
+                const int k = ks * 4 + lk;
+                float a[4], b[2];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) a[u] = As_[cb][(wm * 64 + u * 16 + lr) * SK + k];
+#pragma unroll
+                for (int v = 0; v < 2; ++v) b[v] = Bs_[cb][(wn * 32 + v * 16 + lr) * SK + k];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int v = 0; v < 2; ++v)
+                        if (wmask & (1 << (2 * u + v)))
+                            acc[u][v] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], b[v], acc[u][v], 0, 0, 0);
+            }
+        }
+        // buffer cb ^ 1 was last read in the previous stage, which every wave
+        // finished before the barrier that ended it
+        if (it + 1 < nk) store(cb ^ 1);
+        __syncthreads();
+    }
+    // FP32 accumulator element r of lane l is D[4 (l / 16) + r][l % 16]
+    const int lq = lane >> 4;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            if (!(wmask & (1 << (2 * u + v)))) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + wm * 64 + u * 16 + 4 * lq + r;
+                const int col = n0 + wn * 32 + v * 16 + lr;
+                if (row < M && col < M) G[(long long)col * ldg + row] = (double)acc[u][v][r];
+            }
+        }
+}
+
 void gram_product_f32(hipStream_t st, int n, int rows, const double* X, int ldx, long long sX,
                       double* G, int ldg, long long sG, int batch)
 {
     if (n <= 0 || batch <= 0) return;
-    gemm_launch<true, false, 0, true, 32, true, float>(st, n, n, rows, 1.0, X, ldx, sX, X, ldx, sX, 0.0,
-                                                       G, ldg, sG, batch);
+    const int g = (n + 127) / 128;
+    hipLaunchKernelGGL(gram_f32_kernel, dim3(g * (g + 1) / 2, 1, batch), dim3(512), 0, st, n, rows, X, ldx,
+                       sX, G, ldg, sG);
 }
 
 void trsm_product(hipStream_t st, int code, int rows, int n, const double* X, int ldx, long long sX,
