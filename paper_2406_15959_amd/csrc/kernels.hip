@@ -231,7 +231,10 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(
     // "along-k":   m (or n) = tid / 4, V consecutive k from (tid % 4) * V.
     constexpr int V = GB_K / 4;
     constexpr int RS = 64 / V;   // threads per k row in the along-row pattern
-    double ra[V], rb[V];
+    // K depth 16: two register sets, so that a stage is fetched two stages
+    // before it is stored to LDS (the LDS size, not the registers, bounds the
+    // occupancy of this variant); K depth 32: one set.
+    double ra[V], rb[V], ra2[V], rb2[V];
     auto loadv = [&](double (&r)[V], const double* p, bool all, auto ok) {
         if (all && aligned16(p)) {
             const double2* q2 = reinterpret_cast<const double2*>(p);
@@ -246,44 +249,44 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(
             for (int e = 0; e < V; ++e) r[e] = ok(e) ? p[e] : 0.0;
         }
     };
-    auto load = [&](int k0) {
+    auto load = [&](double (&xa)[V], double (&xb)[V], int k0) {
         if (!TA) {
             const int kk = k0 + tid / RS, mm = m0 + (tid % RS) * V;
             const double* pa = A + (long long)kk * lda + mm;
-            loadv(ra, pa, kk < kend && mm + V - 1 < M, [&](int e) { return kk < kend && mm + e < M; });
+            loadv(xa, pa, kk < kend && mm + V - 1 < M, [&](int e) { return kk < kend && mm + e < M; });
         } else {
             const int mm = m0 + (tid >> 2), kk = k0 + (tid & 3) * V;
             const double* pa = A + (long long)mm * lda + kk;
-            loadv(ra, pa, mm < M && kk + V - 1 < kend, [&](int e) { return mm < M && kk + e < kend; });
+            loadv(xa, pa, mm < M && kk + V - 1 < kend, [&](int e) { return mm < M && kk + e < kend; });
         }
         if (!TB) {
             const int nn = n0 + (tid >> 2), kk = k0 + (tid & 3) * V;
             const double* pb = B + (long long)nn * ldb + kk;
-            loadv(rb, pb, nn < N && kk + V - 1 < kend, [&](int e) { return nn < N && kk + e < kend; });
+            loadv(xb, pb, nn < N && kk + V - 1 < kend, [&](int e) { return nn < N && kk + e < kend; });
         } else {
             const int kk = k0 + tid / RS, nn = n0 + (tid % RS) * V;
             const double* pb = B + (long long)kk * ldb + nn;
-            loadv(rb, pb, kk < kend && nn + V - 1 < N, [&](int e) { return kk < kend && nn + e < N; });
+            loadv(xb, pb, kk < kend && nn + V - 1 < N, [&](int e) { return kk < kend && nn + e < N; });
         }
     };
-    auto store = [&](int b) {
+    auto store = [&](int b, const double (&xa)[V], const double (&xb)[V]) {
         if (!TA) {
             const int k = tid / RS, m = (tid % RS) * V;
 #pragma unroll
-            for (int e = 0; e < V; ++e) As(b, k, m + e) = (CT)ra[e];
+            for (int e = 0; e < V; ++e) As(b, k, m + e) = (CT)xa[e];
         } else {
             const int m = tid >> 2, k = (tid & 3) * V;
 #pragma unroll
-            for (int e = 0; e < V; ++e) As(b, k + e, m) = (CT)ra[e];
+            for (int e = 0; e < V; ++e) As(b, k + e, m) = (CT)xa[e];
         }
         if (!TB) {
             const int nn = tid >> 2, k = (tid & 3) * V;
 #pragma unroll
-            for (int e = 0; e < V; ++e) Bs(b, k + e, nn) = (CT)rb[e];
+            for (int e = 0; e < V; ++e) Bs(b, k + e, nn) = (CT)xb[e];
         } else {
             const int k = tid / RS, nn = (tid % RS) * V;
 #pragma unroll
-            for (int e = 0; e < V; ++e) Bs(b, k, nn + e) = (CT)rb[e];
+            for (int e = 0; e < V; ++e) Bs(b, k, nn + e) = (CT)xb[e];
         }
     };
 
@@ -345,33 +348,61 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(
                 }
     }
     const int nk = (kend > kbeg) ? (kend - kbeg + GB_K - 1) / GB_K : 0;
-    if (nk > 0) {
-        load(kbeg);
-        store(0);
+    auto live = [&](int k0) {   // blocks with work in the K stage starting at k0
+        int mk = wmask;
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            const int C0 = n0 + wn * 32 + v * 16;
+            const bool dead = (KMODE == 2 && k0 >= C0 + 16) || (KMODE == 1 && k0 + GB_K <= C0);
+            if (dead) mk &= ~((1 << v) | (1 << (2 + v)));
+        }
+        return mk;
+    };
+    if constexpr (NBUF == 2) {
+        // Stage it is computed from LDS buffer it % 2.  Register set it % 2
+        // receives stage it + 2 at the start of step it (it held stage it,
+        // stored in step it - 1), and the other set, holding stage it + 1
+        // since step it - 1, is stored into buffer (it + 1) % 2 after the
+        // compute (that buffer was last read in step it - 1, which every wave
+        // finished before the barrier that ended it).
+        auto step = [&](int it, auto par) {
+            constexpr bool odd = decltype(par)::value != 0;
+            const int k0 = kbeg + it * GB_K;
+            if (it + 2 < nk) {
+                if constexpr (odd) load(ra2, rb2, k0 + 2 * GB_K);
+                else load(ra, rb, k0 + 2 * GB_K);
+            }
+            const int mk = live(k0);
+            if (mk) stage(mk, odd ? 1 : 0);
+            if (it + 1 < nk) {
+                if constexpr (odd) store(0, ra, rb);
+                else store(1, ra2, rb2);
+            }
+            __syncthreads();
+        };
+        if (nk > 0) {
+            load(ra, rb, kbeg);
+            store(0, ra, rb);
+            if (nk > 1) load(ra2, rb2, kbeg + GB_K);
+            __syncthreads();
+            for (int it = 0; it < nk; it += 2) {
+                step(it, std::integral_constant<int, 0>{});
+                if (it + 1 < nk) step(it + 1, std::integral_constant<int, 1>{});
+            }
+        }
+    } else if (nk > 0) {
+        load(ra, rb, kbeg);
+        store(0, ra, rb);
         __syncthreads();
         for (int it = 0; it < nk; ++it) {
             const int k0 = kbeg + it * GB_K;
-            const int cb = NBUF == 2 ? (it & 1) : 0;
-            if (it + 1 < nk) load(k0 + GB_K);
-            int mk = wmask;
-#pragma unroll
-            for (int v = 0; v < 2; ++v) {
-                const int C0 = n0 + wn * 32 + v * 16;
-                const bool dead = (KMODE == 2 && k0 >= C0 + 16) || (KMODE == 1 && k0 + GB_K <= C0);
-                if (dead) mk &= ~((1 << v) | (1 << (2 + v)));
-            }
-            if (mk) stage(mk, cb);
-            if constexpr (NBUF == 2) {
-                // buffer cb ^ 1 was last read in the previous stage, which
-                // every wave finished before the barrier that ended it
-                if (it + 1 < nk) store(cb ^ 1);
+            if (it + 1 < nk) load(ra, rb, k0 + GB_K);
+            const int mk = live(k0);
+            if (mk) stage(mk, 0);
+            __syncthreads();
+            if (it + 1 < nk) {
+                store(0, ra, rb);
                 __syncthreads();
-            } else {
-                __syncthreads();
-                if (it + 1 < nk) {
-                    store(0);
-                    __syncthreads();
-                }
             }
         }
     }
