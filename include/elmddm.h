@@ -301,12 +301,12 @@ elmddm_status elmddm_plan_set_mode(elmddm_plan* plan, int32_t mode);
 /* Time the candidate kernels for the two large local products (the Gram
  * matrices of the CholeskyQR passes and the triangular solves) on this plan's
  * shapes and keep the fastest for later solves: the 64 x 64 tile kernel in
- * four variants (K depth 16/32, XCD-aware tile order on/off) and the strip
- * kernel with 16T-wide tiles, T = 4..8.  Overwrites the plan's workspace
- * (call before a solve, not between a solve and elmddm_get_schur); runs
- * synchronously on stream.  Candidates are tried in the order -4, -2, -3,
- * -1, 8, 7, 6, 5, 4 (lower HBM traffic first) and a later one is kept only
- * if it is at least 2% faster, so near-ties do not flip between runs.
+ * four variants (K depth 16 with two LDS buffers or 32 with one, XCD-aware
+ * tile order on/off) and the strip kernel with 16T-wide tiles, T = 4..8.
+ * Overwrites the plan's workspace (call before a solve, not between a solve
+ * and elmddm_get_schur); runs synchronously on stream.  Candidates are tried
+ * in the fixed order -4, -2, -3, -1, 8, 7, 6, 5, 4 and a later one is kept
+ * only if it is at least 2% faster, so near-ties do not flip between runs.
  * choice (NULL or int32[2]) receives the codes of the kernels kept: < 0 is
  * the 64 x 64 kernel variant (-1 - code: bit 1 K depth 32, bit 0 XCD-aware
  * tile order), >= 4 the strip width T. */

@@ -1362,9 +1362,10 @@ elmddm_status elmddm_autotune(elmddm_plan* P, void* stream, int32_t* choice)
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return check_launch("autotune events");
-    // lowest HBM traffic first (XCD-aware tile order, deeper K stage); a
-    // later candidate replaces the kept one only if it is 2% faster, so
-    // candidates within timing noise of each other do not flip between runs
+    // XCD-aware tile order first (it reads X once per XCD instead of up to
+    // eight times); a later candidate replaces the kept one only if it is 2%
+    // faster, so candidates within timing noise of each other do not flip
+    // between runs
     const int codes[] = {-4, -2, -3, -1, 8, 7, 6, 5, 4};
     auto time_it = [&](auto&& fn) {
         fn();
