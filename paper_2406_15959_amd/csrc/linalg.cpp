@@ -15,8 +15,12 @@ void blocked_potrf(hipStream_t st, double* A, int lda, long long sA, int Mrows, 
 {
     if (tau < 0.0) tau = 64.0 * n * 0x1p-53;
     if (dsave) save_diag(st, A, lda, sA, n, dsave, sS, batch);
-    for (int j = 0; j < n; j += NB) {
-        const int jb = std::min(NB, n - j);
+    // Block columns are taken in pairs [j, j2) and [j2, j3): the panel of the
+    // first updates only the second block column, and one rank-(jb + jb2)
+    // update with both panels then brings the trailing matrix [j3, Mrows) x
+    // [j3, n) up to date: the trailing matrix is read and written once per
+    // 128 columns instead of once per 64.
+    auto factor_block = [&](int j, int jb) {   // diagonal block, then its panel rows [j + jb, Mrows)
         double* Dj = Dinv + (long long)(j / NB) * NB * NB;
         potrf_diag(st, A, lda, sA, j, jb, Dj, sD, Linv, ldl, sL, info, pass, batch, dsave, sS, tau,
                    nullptr, 0);
@@ -25,10 +29,24 @@ void blocked_potrf(hipStream_t st, double* A, int lda, long long sA, int Mrows, 
             double* panel = A + (long long)j * lda + (j + jb);
             gemm_f64(st, false, true, 0, false, Mb, jb, jb, 1.0, panel, lda, sA, Dj, NB, sD, 0.0,
                      panel, lda, sA, batch);
-            const int Nt = n - j - jb;
-            if (Nt > 0)
-                gemm_f64(st, false, true, 0, true, Mb, Nt, jb, -1.0, panel, lda, sA, panel, lda, sA,
-                         1.0, A + (long long)(j + jb) * lda + (j + jb), lda, sA, batch);
+        }
+    };
+    for (int j = 0; j < n; j += 2 * NB) {
+        const int jb = std::min(NB, n - j);
+        factor_block(j, jb);
+        const int j2 = j + jb;
+        const int jb2 = std::min(NB, n - j2);
+        if (jb2 <= 0) break;
+        // block column j2, rows [j2, Mrows): A -= L[., j:j2] L[j2:j2+jb2, j:j2]^T
+        const double* L1 = A + (long long)j * lda + j2;
+        gemm_f64(st, false, true, 0, false, Mrows - j2, jb2, jb, -1.0, L1, lda, sA, L1, lda, sA, 1.0,
+                 A + (long long)j2 * lda + j2, lda, sA, batch);
+        factor_block(j2, jb2);
+        const int j3 = j2 + jb2;
+        if (j3 < n) {
+            const double* L12 = A + (long long)j * lda + j3;   // rows [j3, Mrows) of block columns j, j2
+            gemm_f64(st, false, true, 0, true, Mrows - j3, n - j3, jb + jb2, -1.0, L12, lda, sA, L12, lda,
+                     sA, 1.0, A + (long long)j3 * lda + j3, lda, sA, batch);
         }
     }
     if (!Linv) return;

@@ -180,7 +180,8 @@ def _check_gemm(hooks, ta, tb, kmode, lower, M, N, K, batch):
         assert err < 1e-13, (z, err)
 
 
-@pytest.mark.parametrize("n,extra,batch", [(64, 0, 1), (150, 1, 3), (200, 0, 2), (37, 1, 2), (400, 1, 2)])
+@pytest.mark.parametrize("n,extra,batch", [(64, 0, 1), (150, 1, 3), (200, 0, 2), (37, 1, 2), (400, 1, 2),
+                                           (256, 0, 2), (320, 1, 1), (130, 1, 2)])
 def test_blocked_cholesky_and_inverse(hooks, n, extra, batch):
     import torch
     rng = np.random.default_rng(n + batch)
