@@ -129,7 +129,8 @@ elmddm_status elmddm_plan_create(const elmddm_problem* problem, elmddm_plan** pl
  * c [batch][nsub][neurons]).  All stages run over the whole batch in the same
  * launches.  elmddm_plan_create is elmddm_plan_create_batch with batch = 1.
  * elmddm_assemble writes all batch * nsub subdomains; elmddm_get_schur
- * returns instance 0. */
+ * returns instance 0.  batch * nsub may be at most 65535 (INVALID_ARG
+ * beyond): the subdomains of a batch are a grid dimension of the launches. */
 elmddm_status elmddm_plan_create_batch(const elmddm_problem* problem, int32_t batch,
                                        elmddm_plan** plan);
 

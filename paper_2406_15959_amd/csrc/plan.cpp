@@ -17,6 +17,11 @@
 using namespace elmddm;
 
 namespace {
+
+// The batched kernels index the subdomains of a batch (and the instances)
+// by a grid dimension other than x, which holds at most 65535 blocks.
+constexpr int64_t kMaxSubdomains = 65535;
+
 thread_local std::string g_last_error;
 }
 
@@ -680,8 +685,8 @@ elmddm_status elmddm_plan_create_ex(const elmddm_problem* problem, int32_t batch
     *plan = nullptr;
     elmddm_status st = validate(problem);
     if (st != ELMDDM_OK) return st;
-    if (batch < 1 || (int64_t)batch * problem->nsub_x * problem->nsub_y > (1 << 20))
-        return fail(ELMDDM_INVALID_ARG, "batch must be >= 1 and batch * nsub <= 2^20");
+    if (batch < 1 || (int64_t)batch * problem->nsub_x * problem->nsub_y > kMaxSubdomains)
+        return fail(ELMDDM_INVALID_ARG, "batch must be >= 1 and batch * nsub <= 65535");
     if ((flags & ELMDDM_PLAN_MATRIX_FREE) && (flags & ELMDDM_PLAN_DENSE))
         return fail(ELMDDM_INVALID_ARG, "MATRIX_FREE and DENSE are exclusive");
     elmddm_plan* P = new (std::nothrow) elmddm_plan();
@@ -726,8 +731,8 @@ elmddm_status elmddm_plan_query(const elmddm_problem* problem, int32_t batch, el
     if (!sizes) return fail(ELMDDM_INVALID_ARG, "sizes is NULL");
     elmddm_status st = validate(problem);
     if (st != ELMDDM_OK) return st;
-    if (batch < 1 || (int64_t)batch * problem->nsub_x * problem->nsub_y > (1 << 20))
-        return fail(ELMDDM_INVALID_ARG, "batch must be >= 1 and batch * nsub <= 2^20");
+    if (batch < 1 || (int64_t)batch * problem->nsub_x * problem->nsub_y > kMaxSubdomains)
+        return fail(ELMDDM_INVALID_ARG, "batch must be >= 1 and batch * nsub <= 65535");
     elmddm_plan Q;
     Q.p = *problem;
     Q.B = batch;

@@ -80,6 +80,11 @@ def test_plan_query_sizes_without_a_gpu():
     assert s1.device_bytes > 0 and s3.device_bytes > 2 * s1.device_bytes
     with pytest.raises(B.ElmddmError):
         B.plan_query(p, 0)
+    # batch * nsub is bounded by the launch grid (65535 subdomains)
+    assert B.plan_query(p, 65535 // 6).batch == 65535 // 6
+    with pytest.raises(B.ElmddmError) as e:
+        B.plan_query(p, 65535 // 6 + 1)
+    assert e.value.status == B.INVALID_ARG
 
 
 def test_ragged_problem_draws_are_reproducible_and_cover_the_shapes():
