@@ -142,9 +142,10 @@ void assemble(hipStream_t st, int N, int ngeo, long long nbnd, int ldx, int n, c
 // 2x2 V_MFMA_F64_16X16X4 tiles.
 // MFMA operand layout (16x16x4, f64): lane l holds A[l%16][l/16] and
 // B[l/16][l%16]; the accumulator's element r of lane l is D[4*r + l/16][l%16].
-// Global loads move 8 consecutive doubles per thread (16-byte vector loads
-// when aligned and in bounds); the next K stage is fetched into registers
-// while the current one computes.  Workgroups are renumbered so that each
+// Global loads move GB_K / 4 consecutive doubles per thread (16-byte vector
+// loads when aligned and in bounds); a K stage is fetched into registers two
+// stages (K depth 16) or one stage (K depth 32) before it is stored to LDS,
+// while the stages in between compute.  Workgroups are renumbered so that each
 // XCD (the hardware deals workgroups to the 8 XCDs in turn) receives a
 // contiguous run of tiles, i.e. whole matrices of the batch, and their
 // operands stay in that XCD's L2.
